@@ -1,0 +1,248 @@
+/*
+ * mxe — max-entropy permuted sparse matrix-vector product on MI355X (gfx950).
+ *
+ * C ABI of libmxe.so. The library implements the method of Jain et al.,
+ * "Entropy Maximization in Sparse Matrix by Vector Multiplication": permute
+ * the rows and columns of a CSR matrix at random, (P_r y) = (P_r A P_c)(P_c^-1 x)
+ * (Section 1, Eq. 1; Section 3), measure how evenly the nonzeros spread with
+ * the Shannon entropy of a 2D block histogram (Section 4, Eq. eq:entropy;
+ * Section 5), and multiply the permuted, resident matrix by dense vectors
+ * (Section 2). Every step runs in HIP kernels on the GPU.
+ *
+ * Conventions shared by every call
+ *   - Matrices are canonical CSR (Section 2): row_ptr[nrows+1] int32 with
+ *     row_ptr[0] = 0, nondecreasing, row_ptr[nrows] = nnz; col_idx[nnz] int32 in
+ *     [0, ncols), strictly increasing inside a row (duplicates are rejected);
+ *     explicit zeros are kept and count as entries. nnz < 2^31.
+ *   - Permutations are in new-to-old (gather) form: row i' of B = P_r A P_c is
+ *     row rperm[i'] of A, column j' of B is column cperm[j'] of A. Hence
+ *     x' = P_c^-1 x is x'[j'] = x[cperm[j']] and y' = P_r y is y'[i'] = y[rperm[i']].
+ *   - Dense operands X (ncols x k) and Y (nrows x k) are row-major with leading
+ *     dimension ld >= k, in device memory owned by the caller. They are FP64
+ *     for matrices stored in MXE_F64 and FP32 for MXE_F32 / MXE_BF16 storage.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream). Calls
+ *     taking a stream are stream-ordered and return before the device work ends,
+ *     unless stated otherwise.
+ *   - Errors are reported by status only; nothing throws across the ABI. A
+ *     failing call leaves its outputs unspecified and changes no handle.
+ *     mxe_last_error() returns this thread's detail text for the last failure.
+ *   - Calls on one context are serialized internally; mxe_submit and mxe_wait
+ *     may be called from any thread.
+ */
+#ifndef MXE_H
+#define MXE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MXE_ABI_VERSION 1
+
+typedef enum mxe_status {
+    MXE_OK = 0,
+    MXE_ERR_INVALID_ARG = 1,    /* a NULL pointer, negative size, k < 1, ld < k, grid out of range */
+    MXE_ERR_INVALID_CSR = 2,    /* row_ptr / col_idx break the canonical CSR rules above */
+    MXE_ERR_NOT_FOUND = 3,      /* unknown or released handle */
+    MXE_ERR_BUSY = 4,           /* release of a matrix with queued or running work */
+    MXE_ERR_BUDGET = 5,         /* the HBM budget given to mxe_create would be exceeded */
+    MXE_ERR_OUT_OF_MEMORY = 6,  /* device allocation failed */
+    MXE_ERR_UNSUPPORTED = 7,    /* valid request this build does not handle */
+    MXE_ERR_TIMEOUT = 8,        /* mxe_wait timed out; the request is still live */
+    MXE_ERR_DEVICE = 9,         /* HIP runtime error or no usable gfx950 device */
+    MXE_ERR_INEXACT = 10        /* entropy: correct rounding could not be certified */
+} mxe_status;
+
+typedef enum mxe_dtype {        /* storage type of matrix values */
+    MXE_F64 = 0,
+    MXE_F32 = 1,                /* rounded once, to nearest-even, from the FP64 input */
+    MXE_BF16 = 2                /* rounded once, to nearest-even, from the FP64 input */
+} mxe_dtype;
+
+/* flags */
+#define MXE_INPUT_DEVICE    0x1u  /* register: the three arrays are device pointers */
+#define MXE_OUTPUT_DEVICE   0x1u  /* get_permutation / export: outputs are device pointers */
+#define MXE_ROWS            0x1u  /* permute mode: random row permutation ("R") */
+#define MXE_COLS            0x2u  /* permute mode: random column permutation */
+#define MXE_SPACE_PERMUTED  0x0u  /* spmv: X, Y are in the permuted index space */
+#define MXE_SPACE_ORIGINAL  0x1u  /* spmv: X, Y are in A's index space (gather/scatter inside) */
+
+typedef struct mxe_ctx mxe_ctx;
+typedef int64_t mxe_mat;        /* matrix handle, > 0 */
+typedef int64_t mxe_plan;       /* batch plan handle, > 0 */
+typedef int64_t mxe_ticket;     /* serving request handle, > 0 */
+
+typedef struct mxe_matrix_desc {
+    int32_t nrows, ncols;
+    int64_t nnz;
+    int32_t storage;            /* mxe_dtype */
+    int32_t permuted;           /* 1 if made by mxe_permute */
+    mxe_mat parent;             /* the matrix it was permuted from, else 0 */
+    uint64_t seed;              /* permute seed, else 0 */
+    uint32_t mode;              /* permute mode, else 0 */
+    uint64_t device_bytes;      /* HBM held for this matrix */
+    int32_t max_row;            /* longest row */
+    double mean_row;            /* nnz / nrows */
+} mxe_matrix_desc;
+
+/* --- library and context -------------------------------------------------- */
+
+const char *mxe_status_string(mxe_status s);
+/* Detail of this thread's last failed call; never NULL; valid until the next call. */
+const char *mxe_last_error(void);
+int32_t mxe_abi_version(void);
+
+/* Creates a context on HIP device `device`. hbm_budget_bytes caps the HBM the
+ * context holds for resident matrices and in-flight serving work (0 = no cap).
+ * Returns MXE_ERR_DEVICE if the device is missing or is not gfx950. */
+mxe_status mxe_create(int32_t device, uint64_t hbm_budget_bytes, mxe_ctx **out);
+/* Waits for all work, stops the serving loop, frees every matrix and plan. */
+mxe_status mxe_destroy(mxe_ctx *ctx);
+
+/* Checks canonical CSR (Section 2) on the host; needs no device or context.
+ * Returns MXE_OK, MXE_ERR_INVALID_ARG or MXE_ERR_INVALID_CSR. */
+mxe_status mxe_validate_csr(int32_t nrows, int32_t ncols, int64_t nnz,
+                            const int32_t *row_ptr, const int32_t *col_idx);
+
+/* --- matrices --------------------------------------------------------------- */
+
+/* Copies a CSR matrix into HBM, storing values as `storage`. Host inputs are
+ * validated before any device work; device inputs (MXE_INPUT_DEVICE) are
+ * validated after a staging copy of row_ptr and col_idx. The caller may free
+ * its arrays when the call returns (it synchronizes). Values are FP64. */
+mxe_status mxe_register_matrix(mxe_ctx *ctx, int32_t nrows, int32_t ncols, int64_t nnz,
+                               const int32_t *row_ptr, const int32_t *col_idx,
+                               const double *vals, mxe_dtype storage, uint32_t flags,
+                               mxe_mat *out);
+
+/* The randomization of Section 3 / Eq. 1: B = P_r A P_c in canonical CSR,
+ * with P_r drawn when mode has MXE_ROWS and P_c when it has MXE_COLS (identity
+ * otherwise). The permutation of n items is the stable ascending order of n
+ * 64-bit keys, key(i) = i-th output of SplitMix64 started at the stream seed;
+ * the row stream's seed is the first SplitMix64 output started at `seed`, the
+ * column stream's the second. Equal seeds give bit-identical B. B's rows are
+ * re-sorted by new column; values move bit-exactly. B holds A alive. */
+mxe_status mxe_permute(mxe_ctx *ctx, mxe_mat a, uint64_t seed, uint32_t mode,
+                       void *stream, mxe_mat *out_b);
+
+/* Copies B's permutations (new-to-old, nrows / ncols int32) to host memory,
+ * or device memory with MXE_OUTPUT_DEVICE; either pointer may be NULL.
+ * Synchronizes `stream`. For an unpermuted matrix both are the identity. */
+mxe_status mxe_get_permutation(mxe_ctx *ctx, mxe_mat b, int32_t *rperm, int32_t *cperm,
+                               uint32_t flags, void *stream);
+
+/* Copies the stored CSR out (vals in the storage type: double, float or
+ * uint16 BF16 bits). Host outputs unless MXE_OUTPUT_DEVICE. Synchronizes. */
+mxe_status mxe_export_csr(mxe_ctx *ctx, mxe_mat m, int32_t *row_ptr, int32_t *col_idx,
+                          void *vals, uint32_t flags, void *stream);
+
+mxe_status mxe_matrix_info(mxe_ctx *ctx, mxe_mat m, mxe_matrix_desc *out);
+
+/* Releases a handle. A permuted matrix keeps its parent's memory until it is
+ * released too. Returns MXE_ERR_BUSY while serving work on it is queued or
+ * running. */
+mxe_status mxe_release(mxe_ctx *ctx, mxe_mat m);
+
+/* --- measure (Sections 4 and 5) --------------------------------------------- */
+
+/* Block-grid nonzero entropy. Entry (i, j) falls in block
+ * (floor(i*grid_rows/nrows), floor(j*grid_cols/ncols)), computed exactly;
+ * H = -sum p log p over bins with p = count / nnz > 0 (Eq. eq:entropy),
+ * returned correctly rounded to FP64 in bits (h_bits) and nats (h_nats,
+ * may be NULL). An empty matrix, or one whose entries share one block, has
+ * H = 0. hist (grid_rows*grid_cols int64, row-major, host memory) may be NULL.
+ * 1 <= grid_rows, grid_cols <= 2^20. Synchronizes `stream`. Returns
+ * MXE_ERR_INEXACT (values still written) in the rare case that the
+ * double-double evaluation cannot certify the rounding. */
+mxe_status mxe_entropy(mxe_ctx *ctx, mxe_mat m, int32_t grid_rows, int32_t grid_cols,
+                       void *stream, double *h_bits, double *h_nats, int64_t *hist);
+
+/* --- products (Section 2) --------------------------------------------------- */
+
+/* Y = M X for one matrix, k >= 1 right-hand sides (X: ncols x k, Y: nrows x k).
+ * For a permuted B and MXE_SPACE_ORIGINAL, X and Y are in A's index space:
+ * the call gathers X by cperm, multiplies, and scatters Y by rperm (Eq. 1).
+ * FP64 storage accumulates in FP64; FP32/BF16 storage accumulates in FP32.
+ * The kernel variant is the autotuned one for (matrix, k) (mxe_tune). */
+mxe_status mxe_spmv(mxe_ctx *ctx, mxe_mat m, int32_t k, const void *X, int64_t ldx,
+                    void *Y, int64_t ldy, uint32_t flags, void *stream);
+
+/* x' = P_c^-1 x: Xp[j'] = X[cperm[j']] (k columns). */
+mxe_status mxe_gather_x(mxe_ctx *ctx, mxe_mat b, int32_t k, const void *X, int64_t ldx,
+                        void *Xp, int64_t ldxp, void *stream);
+/* y = P_r^-1 y': Y[rperm[i']] = Yp[i'] (k columns). */
+mxe_status mxe_scatter_y(mxe_ctx *ctx, mxe_mat b, int32_t k, const void *Yp, int64_t ldyp,
+                         void *Y, int64_t ldy, void *stream);
+
+/* SpMV kernel variants. A variant id packs the kernel family and its lane
+ * count per row: family MXE_VAR_GROUP with lanes 1..64 (rows per wavefront =
+ * 64 / lanes), MXE_VAR_BINNED (row-length bins, each with its own lanes), or
+ * MXE_VAR_MERGE (merge-path split of rows + nonzeros, equal work per group), or
+ * MXE_VAR_SLAB with lanes = slab size in units of 64 KiB (1..64): a column-slab layout,
+ * built once per matrix and right-hand-side class, whose workgroups keep
+ * their rows' partial sums in LDS and gather x one L2-sized slab at a time. */
+#define MXE_VAR_GROUP   0x000
+#define MXE_VAR_BINNED  0x100
+#define MXE_VAR_MERGE   0x200
+#define MXE_VAR_SLAB    0x300
+#define MXE_VARIANT(family, lanes) ((family) | (lanes))
+
+/* Times the candidate variants for (m, k) on the device and caches the
+ * fastest; returns it in *variant (may be NULL). Synchronizes. */
+mxe_status mxe_tune(mxe_ctx *ctx, mxe_mat m, int32_t k, void *stream, int32_t *variant);
+/* Forces a variant for (m, k); variant 0 clears the choice (retune on use). */
+mxe_status mxe_set_variant(mxe_ctx *ctx, mxe_mat m, int32_t k, int32_t variant);
+
+/* --- batches: many matrices, one persistent launch ------------------------- */
+
+typedef struct mxe_item {
+    mxe_mat mat;
+    int32_t k;
+    const void *X;
+    int64_t ldx;
+    void *Y;
+    int64_t ldy;
+    uint32_t flags;             /* MXE_SPACE_PERMUTED only in batches */
+} mxe_item;
+
+/* One persistent launch computes every item: workgroups pull (item, row tile)
+ * descriptors from a device work list. */
+mxe_status mxe_spmv_batch(mxe_ctx *ctx, int32_t count, const mxe_item *items, void *stream);
+
+/* Plans a batch once (autotunes each item, builds the work list) and captures
+ * the launch in a HIP graph; mxe_batch_launch replays it. Items passed to
+ * launch must name the same matrices and k in the same order; their X / Y
+ * pointers may change (the descriptors are rewritten in device memory before
+ * the replay). items == NULL replays with the planned pointers. */
+mxe_status mxe_batch_create(mxe_ctx *ctx, int32_t count, const mxe_item *items, mxe_plan *out);
+mxe_status mxe_batch_launch(mxe_ctx *ctx, mxe_plan plan, const mxe_item *items, void *stream);
+mxe_status mxe_batch_destroy(mxe_ctx *ctx, mxe_plan plan);
+
+/* --- serving: continuous batching of requests on resident matrices -------- */
+
+typedef struct mxe_serve_config {
+    int32_t streams;            /* device streams the loop issues on (>= 1) */
+    int32_t max_inflight;       /* requests on the device at once (>= 1) */
+    int32_t max_merge_k;        /* merged right-hand sides per launch (1..16) */
+} mxe_serve_config;
+
+/* Starts the serving loop. Requests are admitted while the in-flight bytes
+ * (matrix stream plus vectors) stay within the context budget and a slot is
+ * free; queued requests on the same matrix are merged into one multi-RHS
+ * product up to max_merge_k; work overlaps on `streams` device streams. */
+mxe_status mxe_serve_start(mxe_ctx *ctx, const mxe_serve_config *cfg);
+/* Queues a request (X, Y stay owned by the caller and must stay alive until
+ * mxe_wait returns MXE_OK for it). Thread-safe. */
+mxe_status mxe_submit(mxe_ctx *ctx, const mxe_item *req, mxe_ticket *out);
+/* Blocks until the request is done (timeout_us < 0: forever). On MXE_OK the
+ * ticket is retired and *latency_us (may be NULL) holds submit-to-completion
+ * time. MXE_ERR_TIMEOUT leaves the ticket live. Thread-safe. */
+mxe_status mxe_wait(mxe_ctx *ctx, mxe_ticket t, int64_t timeout_us, double *latency_us);
+/* Drains queued and running requests, then stops the loop. */
+mxe_status mxe_serve_stop(mxe_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MXE_H */

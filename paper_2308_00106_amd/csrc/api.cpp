@@ -1,0 +1,995 @@
+// C ABI of libmxe.so: context, handle table, CSR validation, HBM budget,
+// permutation / entropy / SpMV entry points, the SpMV autotuner and batch
+// plans captured in HIP graphs. See include/mxe.h for the contract.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <limits>
+
+#include "device_common.h"
+#include "runtime.h"
+
+namespace mxe {
+
+// ---- errors -------------------------------------------------------------------
+
+namespace {
+thread_local std::string g_last_error;
+}
+
+void set_error(const std::string &msg) { g_last_error = msg; }
+
+mxe_status fail(mxe_status s, const std::string &msg) {
+    set_error(msg);
+    return s;
+}
+
+mxe_status hip_fail(hipError_t e, const char *what) {
+    char buf[512];
+    snprintf(buf, sizeof buf, "%s failed: %s", what, hipGetErrorString(e));
+    set_error(buf);
+    return e == hipErrorOutOfMemory ? MXE_ERR_OUT_OF_MEMORY : MXE_ERR_DEVICE;
+}
+
+int elem_bytes_of(mxe_dtype d) { return d == MXE_F64 ? 8 : 4; }
+static int val_bytes_of(mxe_dtype d) { return d == MXE_F64 ? 8 : d == MXE_F32 ? 4 : 2; }
+static int vtype_of(mxe_dtype d) { return d == MXE_F64 ? VAL_F64 : d == MXE_F32 ? VAL_F32 : VAL_BF16; }
+
+namespace {
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) (void)hipSetDevice(dev);
+    }
+    ~DeviceGuard() {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+// Stream-ordered allocation from the device's pool (freed blocks stay cached).
+struct Scratch {
+    void *p = nullptr;
+    hipStream_t s = nullptr;
+    Scratch() = default;
+    Scratch(const Scratch &) = delete;
+    ~Scratch() {
+        if (p) (void)hipFreeAsync(p, s);
+    }
+    mxe_status alloc(size_t bytes, hipStream_t stream) {
+        s = stream;
+        hipError_t e = hipMallocAsync(&p, std::max<size_t>(bytes, 256), stream);
+        if (e != hipSuccess) {
+            p = nullptr;
+            return hip_fail(e, "hipMallocAsync(workspace)");
+        }
+        return MXE_OK;
+    }
+};
+
+mxe_status dev_alloc(Matrix &m, void **p, size_t bytes, hipStream_t s) {
+    hipError_t e = hipMallocAsync(p, std::max<size_t>(bytes, 256), s);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        return hip_fail(e, "hipMallocAsync(matrix)");
+    }
+    m.allocs.push_back(*p);
+    return MXE_OK;
+}
+
+uint64_t csr_bytes(int32_t nrows, int64_t nnz, mxe_dtype st) {
+    return 4ull * (uint64_t)(nrows + 1) + (uint64_t)nnz * (4ull + (uint64_t)val_bytes_of(st));
+}
+
+mxe_status reserve(mxe_ctx *ctx, uint64_t bytes) {
+    uint64_t cur = ctx->used.load();
+    for (;;) {
+        if (ctx->budget && cur + bytes > ctx->budget) {
+            char buf[256];
+            snprintf(buf, sizeof buf, "HBM budget exceeded: %llu held + %llu requested > %llu",
+                     (unsigned long long)cur, (unsigned long long)bytes,
+                     (unsigned long long)ctx->budget);
+            return fail(MXE_ERR_BUDGET, buf);
+        }
+        if (ctx->used.compare_exchange_weak(cur, cur + bytes)) return MXE_OK;
+    }
+}
+
+std::shared_ptr<Matrix> make_matrix(mxe_ctx *ctx) {
+    int dev = ctx->device;
+    return std::shared_ptr<Matrix>(new Matrix(), [ctx, dev](Matrix *m) {
+        DeviceGuard g(dev);
+        (void)hipDeviceSynchronize();
+        for (void *p : m->allocs) (void)hipFreeAsync(p, nullptr);
+        if (m->merge_ws) (void)hipFreeAsync(m->merge_ws, nullptr);
+        (void)hipStreamSynchronize(nullptr);
+        ctx->used -= m->bytes;
+        delete m;
+    });
+}
+
+int64_t root_of(const Matrix &m) { return m.parent ? m.parent->id : m.id; }
+
+}  // namespace
+
+std::shared_ptr<Matrix> find_matrix(mxe_ctx *ctx, mxe_mat h) {
+    auto it = ctx->mats.find(h);
+    return it == ctx->mats.end() ? nullptr : it->second;
+}
+
+uint64_t request_bytes(const Matrix &A, int32_t k) {
+    return csr_bytes(A.nrows, A.nnz, A.storage) +
+           (uint64_t)k * ((uint64_t)A.ncols + A.nrows) * elem_bytes_of(A.storage);
+}
+
+// ---- row bins and merge workspace (built once per matrix) -------------------------
+
+static mxe_status ensure_bins(mxe_ctx *, Matrix &A, hipStream_t s) {
+    if (A.bins_ready) return MXE_OK;
+    void *p;
+    mxe_status st = dev_alloc(A, &p, sizeof(int32_t) * ((size_t)A.nrows + 1), s);
+    if (st) return st;
+    A.bin_list = (int32_t *)p;
+    st = dev_alloc(A, &p, sizeof(int32_t) * (kNumBins + 2), s);
+    if (st) return st;
+    A.bin_off_dev = (int32_t *)p;
+    Scratch ws;
+    if ((st = ws.alloc(row_bins_ws_bytes(A.nrows), s))) return st;
+    MXE_HIP(launch_row_bins(A.nrows, A.rp, A.bin_list, A.bin_off_dev, ws.p, s));
+    MXE_HIP(launch_row_max(A.nrows, A.rp, A.bin_off_dev + kNumBins + 1, s));
+    int32_t host[kNumBins + 2];
+    MXE_HIP(hipMemcpyAsync(host, A.bin_off_dev, sizeof host, hipMemcpyDeviceToHost, s));
+    MXE_HIP(hipStreamSynchronize(s));
+    std::memcpy(A.bin_off, host, sizeof A.bin_off);
+    A.max_row = host[kNumBins + 1];
+    A.bins_ready = true;
+    return MXE_OK;
+}
+
+static mxe_status ensure_merge_ws(Matrix &A, hipStream_t s) {
+    if (A.merge_ws) return MXE_OK;
+    hipError_t e = hipMallocAsync(&A.merge_ws, merge_ws_bytes(A.nrows, A.nnz), s);
+    if (e != hipSuccess) {
+        A.merge_ws = nullptr;
+        return hip_fail(e, "hipMallocAsync(merge workspace)");
+    }
+    return MXE_OK;
+}
+
+static SpmvArgs make_args(Matrix &A, int32_t k, const void *X, int64_t ldx, void *Y, int64_t ldy) {
+    SpmvArgs a{};
+    a.nrows = A.nrows;
+    a.ncols = A.ncols;
+    a.nnz = A.nnz;
+    a.rp = A.rp;
+    a.col = A.col;
+    a.val = A.val;
+    a.vtype = vtype_of(A.storage);
+    a.k = k;
+    a.X = X;
+    a.ldx = ldx;
+    a.Y = Y;
+    a.ldy = ldy;
+    a.bin_list = A.bin_list;
+    a.bin_off_host = A.bin_off;
+    a.merge_ws = A.merge_ws;
+    return a;
+}
+
+static int kclass_of(int32_t k) { return k <= 1 ? 1 : k <= 2 ? 2 : k <= 4 ? 4 : k <= 8 ? 8 : 16; }
+
+static TuneKey tune_key(const Matrix &A, int32_t k) {
+    return TuneKey{A.nrows, A.ncols, A.nnz, (int32_t)A.storage, kclass_of(k),
+                   A.seed, A.mode, root_of(A)};
+}
+
+// ---- column-slab layouts (built once per matrix, k class and slab size) ----------
+
+// slab size: `units` x 64 KiB of x
+static int64_t slab_bytes_of(int units) { return (int64_t)units << 16; }
+
+static mxe_status ensure_slab(mxe_ctx *ctx, Matrix &A, int kclass, int units, hipStream_t s,
+                              const Matrix::Slab **out) {
+    const auto key = std::make_pair(kclass, units);
+    auto it = A.slabs.find(key);
+    if (it != A.slabs.end()) {
+        *out = &it->second;
+        return MXE_OK;
+    }
+    Matrix::Slab sl;
+    if (!slab_geometry(A.nrows, A.ncols, kclass, vtype_of(A.storage), ctx->cu_count,
+                       slab_bytes_of(units), &sl.g))
+        return fail(MXE_ERR_UNSUPPORTED, "column-slab layout does not fit this matrix");
+    const int vb = val_bytes_of(A.storage);
+    const size_t noff = slab_offsets_count(sl.g);
+    const uint64_t bytes = 4ull * noff + (uint64_t)A.nnz * (4ull + vb);
+    mxe_status st;
+    if ((st = reserve(ctx, bytes))) return st;
+    A.bytes += bytes;
+    void *p;
+    if ((st = dev_alloc(A, &p, 4 * noff, s))) return st;
+    sl.off = (int32_t *)p;
+    if ((st = dev_alloc(A, &p, 4 * (size_t)A.nnz, s))) return st;
+    sl.idx = (uint32_t *)p;
+    if ((st = dev_alloc(A, &p, (size_t)vb * A.nnz, s))) return st;
+    sl.val = p;
+    Scratch ws;
+    if ((st = ws.alloc(slab_build_ws_bytes(sl.g), s))) return st;
+    MXE_HIP(launch_slab_build(sl.g, A.rp, A.col, A.val, vb, sl.off, sl.idx, sl.val, ws.p, s));
+    *out = &(A.slabs[key] = sl);
+    return MXE_OK;
+}
+
+// Arguments for one launch of `variant`, building what the variant needs.
+static mxe_status prepare_args(mxe_ctx *ctx, Matrix &A, int variant, int32_t k, const void *X,
+                               int64_t ldx, void *Y, int64_t ldy, hipStream_t s, SpmvArgs *a) {
+    const int family = variant & 0xf00;
+    mxe_status st;
+    if (family == MXE_VAR_BINNED && (st = ensure_bins(ctx, A, s))) return st;
+    if (family == MXE_VAR_MERGE && (st = ensure_merge_ws(A, s))) return st;
+    *a = make_args(A, k, X, ldx, Y, ldy);
+    if (family == MXE_VAR_SLAB) {
+        const Matrix::Slab *sl;
+        if ((st = ensure_slab(ctx, A, kclass_of(k), variant & 0xff, s, &sl))) return st;
+        a->slab = &sl->g;
+        a->slab_off = sl->off;
+        a->slab_idx = sl->idx;
+        a->slab_val = sl->val;
+    }
+    return MXE_OK;
+}
+
+// ---- autotuner ---------------------------------------------------------------------
+// Times every variant (GROUP with 1..64 lanes, BINNED, MERGE when k <= 4,
+// SLAB with 1, 2 and 4 MiB slabs when the layout fits) on the matrix itself
+// with scratch vectors and keeps the fastest; also keeps the fastest GROUP
+// lanes for the persistent batch kernel.
+static mxe_status tune(mxe_ctx *ctx, Matrix &A, int32_t k, hipStream_t s, TuneResult *out) {
+    mxe_status st;
+    const int kc = kclass_of(k);
+    const size_t eb = elem_bytes_of(A.storage);
+    Scratch xs, ys;
+    if ((st = xs.alloc(eb * (size_t)std::max(A.ncols, 1) * kc, s))) return st;
+    if ((st = ys.alloc(eb * (size_t)std::max(A.nrows, 1) * kc, s))) return st;
+    MXE_HIP(hipMemsetAsync(xs.p, 0, eb * (size_t)std::max(A.ncols, 1) * kc, s));
+    std::vector<int> cands;
+    for (int l = 1; l <= 64; l <<= 1) cands.push_back(MXE_VARIANT(MXE_VAR_GROUP, l));
+    cands.push_back(MXE_VARIANT(MXE_VAR_BINNED, 0));
+    if (kc <= 4) cands.push_back(MXE_VARIANT(MXE_VAR_MERGE, 0));
+    for (int units : {16, 32, 64}) {                 // 1, 2 and 4 MiB of x per slab
+        SlabGeom g;
+        if (slab_geometry(A.nrows, A.ncols, kc, vtype_of(A.storage), ctx->cu_count,
+                          slab_bytes_of(units), &g))
+            cands.push_back(MXE_VARIANT(MXE_VAR_SLAB, units));
+    }
+    hipEvent_t e0, e1;
+    MXE_HIP(hipEventCreate(&e0));
+    MXE_HIP(hipEventCreate(&e1));
+    const int reps = A.nnz > 4000000 ? 3 : 10;
+    float best = std::numeric_limits<float>::max(), best_group = best;
+    TuneResult r{cands[0], 1};
+    mxe_status result = MXE_OK;
+    for (int v : cands) {
+        SpmvArgs a;
+        if ((result = prepare_args(ctx, A, v, kc, xs.p, kc, ys.p, kc, s, &a))) {
+            if (result == MXE_ERR_UNSUPPORTED) {
+                result = MXE_OK;
+                continue;
+            }
+            break;
+        }
+        hipError_t e = launch_spmv(a, v, s);                  // warm-up
+        for (int i = 0; i < reps && e == hipSuccess; ++i) {
+            if (i == 0) e = hipEventRecord(e0, s);
+            if (e == hipSuccess) e = launch_spmv(a, v, s);
+        }
+        if (e == hipSuccess) e = hipEventRecord(e1, s);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e != hipSuccess) {
+            result = hip_fail(e, "autotune");
+            break;
+        }
+        if (getenv("MXE_LOG"))
+            fprintf(stderr, "[mxe] tune rows=%d nnz=%lld k=%d variant 0x%x: %.2f us\n", A.nrows,
+                    (long long)A.nnz, kc, v, 1e3f * ms / reps);
+        if (ms < best) {
+            best = ms;
+            r.variant = v;
+        }
+        if ((v & 0xf00) == MXE_VAR_GROUP && ms < best_group) {
+            best_group = ms;
+            r.group_lanes = v & 0xff;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (result != MXE_OK) return result;
+    ctx->tuned[tune_key(A, k)] = r;
+    if (out) *out = r;
+    return MXE_OK;
+}
+
+mxe_status ensure_variant(mxe_ctx *ctx, Matrix &A, int32_t k, hipStream_t s, TuneResult *out) {
+    auto it = ctx->tuned.find(tune_key(A, k));
+    if (it != ctx->tuned.end()) {
+        *out = it->second;
+        return MXE_OK;
+    }
+    return tune(ctx, A, k, s, out);
+}
+
+// ---- products -------------------------------------------------------------------------
+
+static mxe_status spmv_core(mxe_ctx *ctx, Matrix &A, int32_t k, const void *X, int64_t ldx,
+                            void *Y, int64_t ldy, hipStream_t s) {
+    const int eb = elem_bytes_of(A.storage);
+    for (int32_t c0 = 0; c0 < k; c0 += 16) {
+        const int32_t kc = std::min<int32_t>(16, k - c0);
+        TuneResult r;
+        mxe_status st = ensure_variant(ctx, A, kc, s, &r);
+        if (st) return st;
+        SpmvArgs a;
+        if ((st = prepare_args(ctx, A, r.variant, kc, (const char *)X + (size_t)c0 * eb, ldx,
+                               (char *)Y + (size_t)c0 * eb, ldy, s, &a)))
+            return st;
+        MXE_HIP(launch_spmv(a, r.variant, s));
+    }
+    return MXE_OK;
+}
+
+mxe_status spmv_internal(mxe_ctx *ctx, Matrix &A, int32_t k, const void *X, int64_t ldx, void *Y,
+                         int64_t ldy, uint32_t flags, hipStream_t s) {
+    if (!(flags & MXE_SPACE_ORIGINAL) || !A.rperm) return spmv_core(ctx, A, k, X, ldx, Y, ldy, s);
+    // Eq. 1: y = P_r^-1 (B (P_c^-1 x))
+    const int eb = elem_bytes_of(A.storage);
+    Scratch xp, yp;
+    mxe_status st;
+    if ((st = xp.alloc((size_t)eb * std::max(A.ncols, 1) * k, s))) return st;
+    if ((st = yp.alloc((size_t)eb * std::max(A.nrows, 1) * k, s))) return st;
+    MXE_HIP(launch_gather_rows(A.ncols, k, A.cperm, X, ldx, xp.p, k, eb, s));
+    if ((st = spmv_core(ctx, A, k, xp.p, k, yp.p, k, s))) return st;
+    MXE_HIP(launch_scatter_rows(A.nrows, k, A.rperm, yp.p, k, Y, ldy, eb, s));
+    return MXE_OK;
+}
+
+}  // namespace mxe
+
+using namespace mxe;
+
+// ============================== C ABI ==========================================
+
+extern "C" {
+
+const char *mxe_status_string(mxe_status s) {
+    switch (s) {
+    case MXE_OK: return "ok";
+    case MXE_ERR_INVALID_ARG: return "invalid argument";
+    case MXE_ERR_INVALID_CSR: return "invalid CSR";
+    case MXE_ERR_NOT_FOUND: return "handle not found";
+    case MXE_ERR_BUSY: return "busy";
+    case MXE_ERR_BUDGET: return "HBM budget exceeded";
+    case MXE_ERR_OUT_OF_MEMORY: return "out of device memory";
+    case MXE_ERR_UNSUPPORTED: return "unsupported";
+    case MXE_ERR_TIMEOUT: return "timeout";
+    case MXE_ERR_DEVICE: return "device error";
+    case MXE_ERR_INEXACT: return "rounding not certified";
+    }
+    return "unknown status";
+}
+
+const char *mxe_last_error(void) { return g_last_error.c_str(); }
+
+int32_t mxe_abi_version(void) { return MXE_ABI_VERSION; }
+
+mxe_status mxe_validate_csr(int32_t nrows, int32_t ncols, int64_t nnz, const int32_t *row_ptr,
+                            const int32_t *col_idx) {
+    if (nrows < 0 || ncols < 0 || nnz < 0 || nnz > INT32_MAX)
+        return fail(MXE_ERR_INVALID_ARG, "negative size or nnz >= 2^31");
+    if (!row_ptr || (nnz > 0 && !col_idx)) return fail(MXE_ERR_INVALID_ARG, "NULL array");
+    if (nnz > 0 && (nrows == 0 || ncols == 0))
+        return fail(MXE_ERR_INVALID_CSR, "entries in an empty shape");
+    if (row_ptr[0] != 0) return fail(MXE_ERR_INVALID_CSR, "row_ptr[0] != 0");
+    if (row_ptr[nrows] != nnz) return fail(MXE_ERR_INVALID_CSR, "row_ptr[nrows] != nnz");
+    for (int32_t i = 0; i < nrows; ++i) {
+        const int32_t a = row_ptr[i], b = row_ptr[i + 1];
+        if (b < a) {
+            char buf[128];
+            snprintf(buf, sizeof buf, "row_ptr decreases at row %d", i);
+            return fail(MXE_ERR_INVALID_CSR, buf);
+        }
+        if (b > nnz) return fail(MXE_ERR_INVALID_CSR, "row_ptr exceeds nnz");
+        for (int32_t e = a; e < b; ++e) {
+            const int32_t c = col_idx[e];
+            if (c < 0 || c >= ncols) {
+                char buf[128];
+                snprintf(buf, sizeof buf, "column %d out of range in row %d", c, i);
+                return fail(MXE_ERR_INVALID_CSR, buf);
+            }
+            if (e > a && c <= col_idx[e - 1]) {
+                char buf[128];
+                snprintf(buf, sizeof buf, "columns not strictly increasing in row %d", i);
+                return fail(MXE_ERR_INVALID_CSR, buf);
+            }
+        }
+    }
+    return MXE_OK;
+}
+
+mxe_status mxe_create(int32_t device, uint64_t hbm_budget_bytes, mxe_ctx **out) {
+    if (!out) return fail(MXE_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || n == 0)
+        return fail(MXE_ERR_DEVICE, "no HIP device");
+    if (device < 0 || device >= n) return fail(MXE_ERR_INVALID_ARG, "device index out of range");
+    hipDeviceProp_t prop;
+    MXE_HIP(hipGetDeviceProperties(&prop, device));
+    if (strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return fail(MXE_ERR_DEVICE, std::string("not a gfx950 device: ") + prop.gcnArchName);
+    DeviceGuard g(device);
+    hipMemPool_t pool;
+    MXE_HIP(hipDeviceGetDefaultMemPool(&pool, device));
+    uint64_t thr = UINT64_MAX;
+    MXE_HIP(hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr));
+    auto *ctx = new mxe_ctx();
+    ctx->device = device;
+    ctx->budget = hbm_budget_bytes;
+    ctx->cu_count = prop.multiProcessorCount;
+    *out = ctx;
+    return MXE_OK;
+}
+
+mxe_status mxe_destroy(mxe_ctx *ctx) {
+    if (!ctx) return fail(MXE_ERR_INVALID_ARG, "ctx is NULL");
+    serve_destroy(ctx);
+    {
+        std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+        DeviceGuard g(ctx->device);
+        (void)hipDeviceSynchronize();
+        for (auto &kv : ctx->plans) {
+            Plan &p = *kv.second;
+            if (p.exec) (void)hipGraphExecDestroy(p.exec);
+            if (p.graph) (void)hipGraphDestroy(p.graph);
+            if (p.capture_stream) (void)hipStreamDestroy(p.capture_stream);
+            if (p.descs_dev) (void)hipFree(p.descs_dev);
+            if (p.counter) (void)hipFree(p.counter);
+        }
+        ctx->plans.clear();
+        ctx->mats.clear();
+    }
+    delete ctx;
+    return MXE_OK;
+}
+
+mxe_status mxe_register_matrix(mxe_ctx *ctx, int32_t nrows, int32_t ncols, int64_t nnz,
+                               const int32_t *row_ptr, const int32_t *col_idx, const double *vals,
+                               mxe_dtype storage, uint32_t flags, mxe_mat *out) {
+    if (!ctx || !out) return fail(MXE_ERR_INVALID_ARG, "ctx or out is NULL");
+    if (storage != MXE_F64 && storage != MXE_F32 && storage != MXE_BF16)
+        return fail(MXE_ERR_INVALID_ARG, "unknown storage dtype");
+    if (flags & ~MXE_INPUT_DEVICE) return fail(MXE_ERR_INVALID_ARG, "unknown flags");
+    if (nrows < 0 || ncols < 0 || nnz < 0 || nnz > INT32_MAX)
+        return fail(MXE_ERR_INVALID_ARG, "negative size or nnz >= 2^31");
+    if (!row_ptr || (nnz > 0 && (!col_idx || !vals))) return fail(MXE_ERR_INVALID_ARG, "NULL array");
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    DeviceGuard g(ctx->device);
+    const bool on_dev = flags & MXE_INPUT_DEVICE;
+    mxe_status st;
+    std::vector<int32_t> hrp, hcol;
+    const int32_t *vrp = row_ptr, *vcol = col_idx;
+    if (on_dev) {               // validate a host staging copy
+        hrp.resize((size_t)nrows + 1);
+        hcol.resize((size_t)nnz);
+        MXE_HIP(hipMemcpy(hrp.data(), row_ptr, 4 * hrp.size(), hipMemcpyDeviceToHost));
+        if (nnz) MXE_HIP(hipMemcpy(hcol.data(), col_idx, 4 * hcol.size(), hipMemcpyDeviceToHost));
+        vrp = hrp.data();
+        vcol = hcol.data();
+    }
+    if ((st = mxe_validate_csr(nrows, ncols, nnz, vrp, vcol))) return st;
+    auto A = make_matrix(ctx);
+    A->nrows = nrows;
+    A->ncols = ncols;
+    A->nnz = nnz;
+    A->storage = storage;
+    const uint64_t bytes = csr_bytes(nrows, nnz, storage);
+    if ((st = reserve(ctx, bytes))) return st;
+    A->bytes = bytes;
+    hipStream_t s = nullptr;
+    void *p;
+    if ((st = dev_alloc(*A, &p, 4 * ((size_t)nrows + 1), s))) return st;
+    A->rp = (int32_t *)p;
+    if ((st = dev_alloc(*A, &p, 4 * (size_t)nnz, s))) return st;
+    A->col = (int32_t *)p;
+    if ((st = dev_alloc(*A, &p, (size_t)val_bytes_of(storage) * nnz, s))) return st;
+    A->val = p;
+    const hipMemcpyKind kind = on_dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    MXE_HIP(hipMemcpyAsync(A->rp, row_ptr, 4 * ((size_t)nrows + 1), kind, s));
+    if (nnz) {
+        MXE_HIP(hipMemcpyAsync(A->col, col_idx, 4 * (size_t)nnz, kind, s));
+        if (storage == MXE_F64) {
+            MXE_HIP(hipMemcpyAsync(A->val, vals, 8 * (size_t)nnz, kind, s));
+        } else {
+            Scratch tmp;
+            if ((st = tmp.alloc(8 * (size_t)nnz, s))) return st;
+            MXE_HIP(hipMemcpyAsync(tmp.p, vals, 8 * (size_t)nnz, kind, s));
+            MXE_HIP(launch_convert_f64((const double *)tmp.p, A->val, nnz, vtype_of(storage), s));
+        }
+    }
+    MXE_HIP(hipStreamSynchronize(s));
+    A->id = ctx->next_id++;
+    ctx->mats[A->id] = A;
+    *out = A->id;
+    return MXE_OK;
+}
+
+mxe_status mxe_permute(mxe_ctx *ctx, mxe_mat a, uint64_t seed, uint32_t mode, void *stream,
+                       mxe_mat *out_b) {
+    if (!ctx || !out_b) return fail(MXE_ERR_INVALID_ARG, "ctx or out_b is NULL");
+    if (mode & ~(MXE_ROWS | MXE_COLS)) return fail(MXE_ERR_INVALID_ARG, "unknown mode bits");
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    DeviceGuard g(ctx->device);
+    auto A = find_matrix(ctx, a);
+    if (!A) return fail(MXE_ERR_NOT_FOUND, "unknown matrix handle");
+    hipStream_t s = (hipStream_t)stream;
+    const int32_t M = A->nrows, N = A->ncols;
+    const uint64_t bytes = csr_bytes(M, A->nnz, A->storage) + 8ull * M + 8ull * N;
+    mxe_status st;
+    if ((st = reserve(ctx, bytes))) return st;
+    auto B = make_matrix(ctx);
+    B->bytes = bytes;
+    B->nrows = M;
+    B->ncols = N;
+    B->nnz = A->nnz;
+    B->storage = A->storage;
+    B->parent = A;
+    B->seed = seed;
+    B->mode = mode;
+    void *p;
+    const int vb = val_bytes_of(A->storage);
+    if ((st = dev_alloc(*B, &p, 4 * ((size_t)M + 1), s))) return st;
+    B->rp = (int32_t *)p;
+    if ((st = dev_alloc(*B, &p, 4 * (size_t)A->nnz, s))) return st;
+    B->col = (int32_t *)p;
+    if ((st = dev_alloc(*B, &p, (size_t)vb * A->nnz, s))) return st;
+    B->val = p;
+    if ((st = dev_alloc(*B, &p, 4 * (size_t)M, s))) return st;
+    B->rperm = (int32_t *)p;
+    if ((st = dev_alloc(*B, &p, 4 * (size_t)M, s))) return st;
+    B->rinv = (int32_t *)p;
+    if ((st = dev_alloc(*B, &p, 4 * (size_t)N, s))) return st;
+    B->cperm = (int32_t *)p;
+    if ((st = dev_alloc(*B, &p, 4 * (size_t)N, s))) return st;
+    B->cinv = (int32_t *)p;
+    // stream seeds: first and second SplitMix64 outputs started at `seed`
+    const uint64_t s_row = sm64_key(seed, 0), s_col = sm64_key(seed, 1);
+    Scratch ws;
+    const size_t ws_bytes = std::max({random_perm_ws_bytes(M), random_perm_ws_bytes(N),
+                                      permuted_row_ptr_ws_bytes(M)});
+    if ((st = ws.alloc(ws_bytes, s))) return st;
+    if (mode & MXE_ROWS) {
+        MXE_HIP(launch_random_perm(M, s_row, B->rperm, B->rinv, ws.p, s));
+    } else {
+        MXE_HIP(launch_iota_i32(B->rperm, M, s));
+        MXE_HIP(launch_iota_i32(B->rinv, M, s));
+    }
+    if (mode & MXE_COLS) {
+        MXE_HIP(launch_random_perm(N, s_col, B->cperm, B->cinv, ws.p, s));
+    } else {
+        MXE_HIP(launch_iota_i32(B->cperm, N, s));
+        MXE_HIP(launch_iota_i32(B->cinv, N, s));
+    }
+    MXE_HIP(launch_permuted_row_ptr(M, A->rp, B->rperm, B->rp, ws.p, s));
+    MXE_HIP(launch_gather_relabel_sort(M, A->rp, A->col, A->val, vb, B->rperm,
+                                       (mode & MXE_COLS) ? B->cinv : nullptr, B->rp, B->col,
+                                       B->val, s));
+    B->id = ctx->next_id++;
+    ctx->mats[B->id] = B;
+    *out_b = B->id;
+    return MXE_OK;
+}
+
+mxe_status mxe_get_permutation(mxe_ctx *ctx, mxe_mat b, int32_t *rperm, int32_t *cperm,
+                               uint32_t flags, void *stream) {
+    if (!ctx) return fail(MXE_ERR_INVALID_ARG, "ctx is NULL");
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    DeviceGuard g(ctx->device);
+    auto B = find_matrix(ctx, b);
+    if (!B) return fail(MXE_ERR_NOT_FOUND, "unknown matrix handle");
+    hipStream_t s = (hipStream_t)stream;
+    const hipMemcpyKind kind = (flags & MXE_OUTPUT_DEVICE) ? hipMemcpyDeviceToDevice
+                                                           : hipMemcpyDeviceToHost;
+    if (B->rperm) {
+        if (rperm && B->nrows) MXE_HIP(hipMemcpyAsync(rperm, B->rperm, 4 * (size_t)B->nrows, kind, s));
+        if (cperm && B->ncols) MXE_HIP(hipMemcpyAsync(cperm, B->cperm, 4 * (size_t)B->ncols, kind, s));
+    } else {
+        if (flags & MXE_OUTPUT_DEVICE) {
+            if (rperm) MXE_HIP(launch_iota_i32(rperm, B->nrows, s));
+            if (cperm) MXE_HIP(launch_iota_i32(cperm, B->ncols, s));
+        } else {
+            if (rperm) for (int32_t i = 0; i < B->nrows; ++i) rperm[i] = i;
+            if (cperm) for (int32_t i = 0; i < B->ncols; ++i) cperm[i] = i;
+        }
+    }
+    MXE_HIP(hipStreamSynchronize(s));
+    return MXE_OK;
+}
+
+mxe_status mxe_export_csr(mxe_ctx *ctx, mxe_mat m, int32_t *row_ptr, int32_t *col_idx, void *vals,
+                          uint32_t flags, void *stream) {
+    if (!ctx) return fail(MXE_ERR_INVALID_ARG, "ctx is NULL");
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    DeviceGuard g(ctx->device);
+    auto A = find_matrix(ctx, m);
+    if (!A) return fail(MXE_ERR_NOT_FOUND, "unknown matrix handle");
+    hipStream_t s = (hipStream_t)stream;
+    const hipMemcpyKind kind = (flags & MXE_OUTPUT_DEVICE) ? hipMemcpyDeviceToDevice
+                                                           : hipMemcpyDeviceToHost;
+    if (row_ptr) MXE_HIP(hipMemcpyAsync(row_ptr, A->rp, 4 * ((size_t)A->nrows + 1), kind, s));
+    if (col_idx && A->nnz) MXE_HIP(hipMemcpyAsync(col_idx, A->col, 4 * (size_t)A->nnz, kind, s));
+    if (vals && A->nnz)
+        MXE_HIP(hipMemcpyAsync(vals, A->val, (size_t)val_bytes_of(A->storage) * A->nnz, kind, s));
+    MXE_HIP(hipStreamSynchronize(s));
+    return MXE_OK;
+}
+
+mxe_status mxe_matrix_info(mxe_ctx *ctx, mxe_mat m, mxe_matrix_desc *out) {
+    if (!ctx || !out) return fail(MXE_ERR_INVALID_ARG, "ctx or out is NULL");
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    DeviceGuard g(ctx->device);
+    auto A = find_matrix(ctx, m);
+    if (!A) return fail(MXE_ERR_NOT_FOUND, "unknown matrix handle");
+    mxe_status st = ensure_bins(ctx, *A, nullptr);
+    if (st) return st;
+    out->nrows = A->nrows;
+    out->ncols = A->ncols;
+    out->nnz = A->nnz;
+    out->storage = A->storage;
+    out->permuted = A->parent ? 1 : 0;
+    out->parent = A->parent ? A->parent->id : 0;
+    out->seed = A->seed;
+    out->mode = A->mode;
+    out->device_bytes = A->bytes;
+    out->max_row = A->max_row;
+    out->mean_row = A->nrows ? (double)A->nnz / A->nrows : 0.0;
+    return MXE_OK;
+}
+
+mxe_status mxe_release(mxe_ctx *ctx, mxe_mat m) {
+    if (!ctx) return fail(MXE_ERR_INVALID_ARG, "ctx is NULL");
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    auto it = ctx->mats.find(m);
+    if (it == ctx->mats.end()) return fail(MXE_ERR_NOT_FOUND, "unknown matrix handle");
+    if (it->second->busy.load() > 0) return fail(MXE_ERR_BUSY, "matrix has serving work in flight");
+    ctx->mats.erase(it);
+    return MXE_OK;
+}
+
+mxe_status mxe_entropy(mxe_ctx *ctx, mxe_mat m, int32_t grid_rows, int32_t grid_cols,
+                       void *stream, double *h_bits, double *h_nats, int64_t *hist) {
+    if (!ctx || !h_bits) return fail(MXE_ERR_INVALID_ARG, "ctx or h_bits is NULL");
+    if (grid_rows < 1 || grid_cols < 1 || grid_rows > (1 << 20) || grid_cols > (1 << 20))
+        return fail(MXE_ERR_INVALID_ARG, "grid dimensions must lie in [1, 2^20]");
+    const int64_t bins = (int64_t)grid_rows * grid_cols;
+    if (bins > (int64_t(1) << 30)) return fail(MXE_ERR_INVALID_ARG, "more than 2^30 bins");
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    DeviceGuard g(ctx->device);
+    auto A = find_matrix(ctx, m);
+    if (!A) return fail(MXE_ERR_NOT_FOUND, "unknown matrix handle");
+    hipStream_t s = (hipStream_t)stream;
+    if (A->nnz == 0) {
+        *h_bits = 0.0;
+        if (h_nats) *h_nats = 0.0;
+        if (hist) std::fill(hist, hist + bins, (int64_t)0);
+        return MXE_OK;
+    }
+    Scratch hdev, ws, res;
+    mxe_status st;
+    if ((st = hdev.alloc(4 * (size_t)bins, s))) return st;
+    if ((st = ws.alloc(entropy_ws_bytes(bins), s))) return st;
+    if ((st = res.alloc(4 * sizeof(double), s))) return st;
+    MXE_HIP(launch_block_hist(A->nrows, A->ncols, A->nnz, A->rp, A->col, grid_rows, grid_cols,
+                              (uint32_t *)hdev.p, s));
+    MXE_HIP(launch_entropy((const uint32_t *)hdev.p, bins, (double *)res.p, ws.p, s));
+    double r[4];
+    MXE_HIP(hipMemcpyAsync(r, res.p, sizeof r, hipMemcpyDeviceToHost, s));
+    std::vector<uint32_t> h32;
+    if (hist) {
+        h32.resize((size_t)bins);
+        MXE_HIP(hipMemcpyAsync(h32.data(), hdev.p, 4 * (size_t)bins, hipMemcpyDeviceToHost, s));
+    }
+    MXE_HIP(hipStreamSynchronize(s));
+    *h_bits = r[0];
+    if (h_nats) *h_nats = r[1];
+    if (hist) for (int64_t i = 0; i < bins; ++i) hist[i] = h32[(size_t)i];
+    if (r[2] != 1.0) return fail(MXE_ERR_INEXACT, "entropy rounding could not be certified");
+    return MXE_OK;
+}
+
+static mxe_status check_dense(const Matrix &A, int32_t k, const void *X, int64_t ldx,
+                              const void *Y, int64_t ldy) {
+    if (k < 1) return fail(MXE_ERR_INVALID_ARG, "k must be >= 1");
+    if (ldx < k || ldy < k) return fail(MXE_ERR_INVALID_ARG, "leading dimension < k");
+    if ((A.ncols > 0 && !X) || (A.nrows > 0 && !Y)) return fail(MXE_ERR_INVALID_ARG, "NULL X or Y");
+    return MXE_OK;
+}
+
+mxe_status mxe_spmv(mxe_ctx *ctx, mxe_mat m, int32_t k, const void *X, int64_t ldx, void *Y,
+                    int64_t ldy, uint32_t flags, void *stream) {
+    if (!ctx) return fail(MXE_ERR_INVALID_ARG, "ctx is NULL");
+    if (flags & ~MXE_SPACE_ORIGINAL) return fail(MXE_ERR_INVALID_ARG, "unknown flags");
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    DeviceGuard g(ctx->device);
+    auto A = find_matrix(ctx, m);
+    if (!A) return fail(MXE_ERR_NOT_FOUND, "unknown matrix handle");
+    mxe_status st = check_dense(*A, k, X, ldx, Y, ldy);
+    if (st) return st;
+    return spmv_internal(ctx, *A, k, X, ldx, Y, ldy, flags, (hipStream_t)stream);
+}
+
+mxe_status mxe_gather_x(mxe_ctx *ctx, mxe_mat b, int32_t k, const void *X, int64_t ldx, void *Xp,
+                        int64_t ldxp, void *stream) {
+    if (!ctx) return fail(MXE_ERR_INVALID_ARG, "ctx is NULL");
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    DeviceGuard g(ctx->device);
+    auto B = find_matrix(ctx, b);
+    if (!B) return fail(MXE_ERR_NOT_FOUND, "unknown matrix handle");
+    if (k < 1 || ldx < k || ldxp < k) return fail(MXE_ERR_INVALID_ARG, "bad k or leading dimension");
+    if (B->ncols > 0 && (!X || !Xp)) return fail(MXE_ERR_INVALID_ARG, "NULL X or Xp");
+    const int eb = elem_bytes_of(B->storage);
+    hipStream_t s = (hipStream_t)stream;
+    if (!B->cperm) {
+        MXE_HIP(launch_copy_cols(B->ncols, k, X, ldx, Xp, ldxp, eb, s));
+        return MXE_OK;
+    }
+    MXE_HIP(launch_gather_rows(B->ncols, k, B->cperm, X, ldx, Xp, ldxp, eb, s));
+    return MXE_OK;
+}
+
+mxe_status mxe_scatter_y(mxe_ctx *ctx, mxe_mat b, int32_t k, const void *Yp, int64_t ldyp, void *Y,
+                         int64_t ldy, void *stream) {
+    if (!ctx) return fail(MXE_ERR_INVALID_ARG, "ctx is NULL");
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    DeviceGuard g(ctx->device);
+    auto B = find_matrix(ctx, b);
+    if (!B) return fail(MXE_ERR_NOT_FOUND, "unknown matrix handle");
+    if (k < 1 || ldy < k || ldyp < k) return fail(MXE_ERR_INVALID_ARG, "bad k or leading dimension");
+    if (B->nrows > 0 && (!Y || !Yp)) return fail(MXE_ERR_INVALID_ARG, "NULL Y or Yp");
+    const int eb = elem_bytes_of(B->storage);
+    hipStream_t s = (hipStream_t)stream;
+    if (!B->rperm) {
+        MXE_HIP(launch_copy_cols(B->nrows, k, Yp, ldyp, Y, ldy, eb, s));
+        return MXE_OK;
+    }
+    MXE_HIP(launch_scatter_rows(B->nrows, k, B->rperm, Yp, ldyp, Y, ldy, eb, s));
+    return MXE_OK;
+}
+
+mxe_status mxe_tune(mxe_ctx *ctx, mxe_mat m, int32_t k, void *stream, int32_t *variant) {
+    if (!ctx) return fail(MXE_ERR_INVALID_ARG, "ctx is NULL");
+    if (k < 1) return fail(MXE_ERR_INVALID_ARG, "k must be >= 1");
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    DeviceGuard g(ctx->device);
+    auto A = find_matrix(ctx, m);
+    if (!A) return fail(MXE_ERR_NOT_FOUND, "unknown matrix handle");
+    TuneResult r;
+    mxe_status st = tune(ctx, *A, std::min(k, 16), (hipStream_t)stream, &r);
+    if (st) return st;
+    if (variant) *variant = r.variant;
+    return MXE_OK;
+}
+
+mxe_status mxe_set_variant(mxe_ctx *ctx, mxe_mat m, int32_t k, int32_t variant) {
+    if (!ctx) return fail(MXE_ERR_INVALID_ARG, "ctx is NULL");
+    if (k < 1) return fail(MXE_ERR_INVALID_ARG, "k must be >= 1");
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    DeviceGuard g(ctx->device);
+    auto A = find_matrix(ctx, m);
+    if (!A) return fail(MXE_ERR_NOT_FOUND, "unknown matrix handle");
+    const TuneKey key = tune_key(*A, std::min(k, 16));
+    if (variant == 0) {
+        ctx->tuned.erase(key);
+        return MXE_OK;
+    }
+    const int family = variant & 0xf00, lanes = variant & 0xff;
+    const bool pow2 = lanes >= 1 && lanes <= 64 && (lanes & (lanes - 1)) == 0;
+    if (family == MXE_VAR_GROUP && !pow2) return fail(MXE_ERR_INVALID_ARG, "lanes must be 1..64, a power of two");
+    if (family != MXE_VAR_GROUP && family != MXE_VAR_BINNED && family != MXE_VAR_MERGE &&
+        family != MXE_VAR_SLAB)
+        return fail(MXE_ERR_INVALID_ARG, "unknown variant family");
+    if (family == MXE_VAR_SLAB) {
+        SlabGeom sg;
+        if (lanes < 1 || lanes > 64) return fail(MXE_ERR_INVALID_ARG, "slab size must be 1..64 x 64 KiB");
+        if (!slab_geometry(A->nrows, A->ncols, kclass_of(k), vtype_of(A->storage), ctx->cu_count,
+                           slab_bytes_of(lanes), &sg))
+            return fail(MXE_ERR_UNSUPPORTED, "column-slab layout does not fit this matrix");
+    }
+    if (family == MXE_VAR_MERGE && kclass_of(k) > 4)
+        return fail(MXE_ERR_UNSUPPORTED, "merge-path variant handles k <= 4");
+    TuneResult r{variant, family == MXE_VAR_GROUP ? lanes : 8};
+    auto it = ctx->tuned.find(key);
+    if (it != ctx->tuned.end() && family != MXE_VAR_GROUP) r.group_lanes = it->second.group_lanes;
+    ctx->tuned[key] = r;
+    return MXE_OK;
+}
+
+// ---- batches ------------------------------------------------------------------------
+
+static mxe_status build_descs(mxe_ctx *ctx, int32_t count, const mxe_item *items, hipStream_t s,
+                              std::vector<BatchDesc> &descs, int32_t &total_tiles) {
+    if (count < 1 || !items) return fail(MXE_ERR_INVALID_ARG, "empty batch");
+    descs.clear();
+    int64_t tiles = 0;
+    for (int32_t i = 0; i < count; ++i) {
+        const mxe_item &it = items[i];
+        auto A = find_matrix(ctx, it.mat);
+        if (!A) return fail(MXE_ERR_NOT_FOUND, "unknown matrix handle in batch");
+        if (it.flags != MXE_SPACE_PERMUTED)
+            return fail(MXE_ERR_UNSUPPORTED, "batches take permuted-space vectors only");
+        if (it.k > 16) return fail(MXE_ERR_UNSUPPORTED, "batches take k <= 16");
+        mxe_status st = check_dense(*A, it.k, it.X, it.ldx, it.Y, it.ldy);
+        if (st) return st;
+        TuneResult r;
+        if ((st = ensure_variant(ctx, *A, it.k, s, &r))) return st;
+        BatchDesc d{};
+        d.rp = A->rp;
+        d.col = A->col;
+        d.val = A->val;
+        d.X = it.X;
+        d.Y = it.Y;
+        d.ldx = it.ldx;
+        d.ldy = it.ldy;
+        d.nrows = A->nrows;
+        d.k = it.k;
+        d.vtype = vtype_of(A->storage);
+        d.lanes = r.group_lanes;
+        d.rows_per_tile = (256 / r.group_lanes) * 4;
+        d.tile_begin = (int32_t)tiles;
+        tiles += (A->nrows + d.rows_per_tile - 1) / d.rows_per_tile;
+        if (tiles > INT32_MAX) return fail(MXE_ERR_UNSUPPORTED, "too many tiles in batch");
+        descs.push_back(d);
+    }
+    total_tiles = (int32_t)tiles;
+    return MXE_OK;
+}
+
+mxe_status mxe_spmv_batch(mxe_ctx *ctx, int32_t count, const mxe_item *items, void *stream) {
+    if (!ctx) return fail(MXE_ERR_INVALID_ARG, "ctx is NULL");
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    DeviceGuard g(ctx->device);
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<BatchDesc> descs;
+    int32_t total = 0;
+    mxe_status st = build_descs(ctx, count, items, s, descs, total);
+    if (st) return st;
+    Scratch dd, ctr;
+    if ((st = dd.alloc(sizeof(BatchDesc) * descs.size(), s))) return st;
+    if ((st = ctr.alloc(sizeof(int32_t), s))) return st;
+    MXE_HIP(hipStreamSynchronize(s));     // pool blocks ready before the blocking copy
+    MXE_HIP(hipMemcpy(dd.p, descs.data(), sizeof(BatchDesc) * descs.size(), hipMemcpyHostToDevice));
+    MXE_HIP(launch_batch_reset((int32_t *)ctr.p, s));
+    MXE_HIP(launch_spmv_batch((const BatchDesc *)dd.p, count, total, (int32_t *)ctr.p,
+                              batch_grid_size(), s));
+    return MXE_OK;
+}
+
+mxe_status mxe_batch_create(mxe_ctx *ctx, int32_t count, const mxe_item *items, mxe_plan *out) {
+    if (!ctx || !out) return fail(MXE_ERR_INVALID_ARG, "ctx or out is NULL");
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    DeviceGuard g(ctx->device);
+    auto plan = std::make_unique<Plan>();
+    mxe_status st = build_descs(ctx, count, items, nullptr, plan->descs, plan->total_tiles);
+    if (st) return st;
+    plan->items.assign(items, items + count);
+    MXE_HIP(hipMalloc(&plan->descs_dev, sizeof(BatchDesc) * plan->descs.size()));
+    MXE_HIP(hipMalloc(&plan->counter, sizeof(int32_t)));
+    MXE_HIP(hipMemcpy(plan->descs_dev, plan->descs.data(), sizeof(BatchDesc) * plan->descs.size(),
+                      hipMemcpyHostToDevice));
+    MXE_HIP(hipStreamCreateWithFlags(&plan->capture_stream, hipStreamNonBlocking));
+    hipStream_t cs = plan->capture_stream;
+    MXE_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    hipError_t e1 = launch_batch_reset(plan->counter, cs);
+    hipError_t e2 = launch_spmv_batch(plan->descs_dev, count, plan->total_tiles, plan->counter,
+                                      batch_grid_size(), cs);
+    hipError_t e3 = hipStreamEndCapture(cs, &plan->graph);
+    if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) {
+        Plan &p = *plan;
+        if (p.graph) (void)hipGraphDestroy(p.graph);
+        (void)hipStreamDestroy(p.capture_stream);
+        (void)hipFree(p.descs_dev);
+        (void)hipFree(p.counter);
+        return hip_fail(e1 != hipSuccess ? e1 : e2 != hipSuccess ? e2 : e3, "batch graph capture");
+    }
+    MXE_HIP(hipGraphInstantiate(&plan->exec, plan->graph, nullptr, nullptr, 0));
+    const int64_t id = ctx->next_id++;
+    ctx->plans[id] = std::move(plan);
+    *out = id;
+    return MXE_OK;
+}
+
+mxe_status mxe_batch_launch(mxe_ctx *ctx, mxe_plan h, const mxe_item *items, void *stream) {
+    if (!ctx) return fail(MXE_ERR_INVALID_ARG, "ctx is NULL");
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    DeviceGuard g(ctx->device);
+    auto it = ctx->plans.find(h);
+    if (it == ctx->plans.end()) return fail(MXE_ERR_NOT_FOUND, "unknown plan handle");
+    Plan &p = *it->second;
+    hipStream_t s = (hipStream_t)stream;
+    if (items) {
+        for (size_t i = 0; i < p.items.size(); ++i) {
+            const mxe_item &a = items[i], &b = p.items[i];
+            if (a.mat != b.mat || a.k != b.k || a.flags != b.flags)
+                return fail(MXE_ERR_INVALID_ARG, "batch items differ from the plan's matrices or k");
+            auto A = find_matrix(ctx, a.mat);
+            if (!A) return fail(MXE_ERR_NOT_FOUND, "unknown matrix handle in batch");
+            mxe_status st = check_dense(*A, a.k, a.X, a.ldx, a.Y, a.ldy);
+            if (st) return st;
+        }
+        bool changed = false;
+        for (size_t i = 0; i < p.items.size(); ++i) {
+            BatchDesc &d = p.descs[i];
+            if (d.X != items[i].X || d.Y != items[i].Y || d.ldx != items[i].ldx ||
+                d.ldy != items[i].ldy) {
+                d.X = items[i].X;
+                d.Y = items[i].Y;
+                d.ldx = items[i].ldx;
+                d.ldy = items[i].ldy;
+                changed = true;
+            }
+            p.items[i] = items[i];
+        }
+        if (changed) {
+            // the previous replay may still read the table: order the rewrite after it
+            MXE_HIP(hipStreamSynchronize(s));
+            MXE_HIP(hipMemcpy(p.descs_dev, p.descs.data(), sizeof(BatchDesc) * p.descs.size(),
+                              hipMemcpyHostToDevice));
+        }
+    }
+    MXE_HIP(hipGraphLaunch(p.exec, s));
+    return MXE_OK;
+}
+
+mxe_status mxe_batch_destroy(mxe_ctx *ctx, mxe_plan h) {
+    if (!ctx) return fail(MXE_ERR_INVALID_ARG, "ctx is NULL");
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    DeviceGuard g(ctx->device);
+    auto it = ctx->plans.find(h);
+    if (it == ctx->plans.end()) return fail(MXE_ERR_NOT_FOUND, "unknown plan handle");
+    Plan &p = *it->second;
+    (void)hipDeviceSynchronize();
+    if (p.exec) (void)hipGraphExecDestroy(p.exec);
+    if (p.graph) (void)hipGraphDestroy(p.graph);
+    if (p.capture_stream) (void)hipStreamDestroy(p.capture_stream);
+    (void)hipFree(p.descs_dev);
+    (void)hipFree(p.counter);
+    ctx->plans.erase(it);
+    return MXE_OK;
+}
+
+// ---- serving (loop in serve.cpp) -------------------------------------------------------
+
+mxe_status mxe_serve_start(mxe_ctx *ctx, const mxe_serve_config *cfg) {
+    if (!ctx || !cfg) return fail(MXE_ERR_INVALID_ARG, "ctx or cfg is NULL");
+    return serve_start(ctx, cfg);
+}
+mxe_status mxe_submit(mxe_ctx *ctx, const mxe_item *req, mxe_ticket *out) {
+    if (!ctx || !req || !out) return fail(MXE_ERR_INVALID_ARG, "ctx, req or out is NULL");
+    return serve_submit(ctx, req, out);
+}
+mxe_status mxe_wait(mxe_ctx *ctx, mxe_ticket t, int64_t timeout_us, double *latency_us) {
+    if (!ctx) return fail(MXE_ERR_INVALID_ARG, "ctx is NULL");
+    return serve_wait(ctx, t, timeout_us, latency_us);
+}
+mxe_status mxe_serve_stop(mxe_ctx *ctx) {
+    if (!ctx) return fail(MXE_ERR_INVALID_ARG, "ctx is NULL");
+    return serve_stop(ctx);
+}
+
+}  // extern "C"

@@ -1,0 +1,153 @@
+// Device helpers shared by the mxe kernels (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mxe {
+
+constexpr int kWave = 64;
+
+// ---------------------------------------------------------------------------
+// Random keys. The permutation of n items is the stable ascending order of
+// key(s, i), the i-th output (i = 0, 1, ...) of SplitMix64 started at state s
+// (Steele, Lea and Flood, OOPSLA 2014). SplitMix64 advances its state by the
+// golden-ratio increment before each output, so output i is the finaliser
+// applied to s + (i + 1) * increment: a counter-based hash, computed per index
+// with no state and no memory traffic.
+// ---------------------------------------------------------------------------
+__host__ __device__ inline uint64_t sm64_key(uint64_t s, uint64_t i) {
+    uint64_t z = s + (i + 1ull) * 0x9e3779b97f4a7c15ull;
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
+
+// ---------------------------------------------------------------------------
+// Exact block index floor(j * g / n) for 0 <= j < n < 2^31, 1 <= g <= 2^20
+// (the product stays below 2^51, exact in FP64). The FP64 quotient is within
+// one of the true floor; one integer correction step makes it exact.
+// ---------------------------------------------------------------------------
+__device__ inline int32_t block_index(int64_t j, int64_t g, int64_t n, double inv_n) {
+    int64_t num = j * g;
+    int64_t q = (int64_t)((double)num * inv_n);
+    if (q * n > num) --q;
+    else if ((q + 1) * n <= num) ++q;
+    return (int32_t)q;
+}
+
+// ---------------------------------------------------------------------------
+// Double-double arithmetic (about 106 significant bits), built from the
+// error-free transformations of Knuth (two-sum) and the exact FMA product.
+// Used to evaluate the entropy accurately enough to certify its rounding.
+// ---------------------------------------------------------------------------
+struct dd { double hi, lo; };
+
+#pragma clang fp contract(off)
+__device__ inline dd two_sum(double a, double b) {
+    double s = a + b;
+    double bb = s - a;
+    double e = (a - (s - bb)) + (b - bb);
+    return {s, e};
+}
+__device__ inline dd quick_two_sum(double a, double b) {   // |a| >= |b|
+    double s = a + b;
+    double e = b - (s - a);
+    return {s, e};
+}
+__device__ inline dd two_prod(double a, double b) {
+    double p = a * b;
+    double e = __builtin_fma(a, b, -p);
+    return {p, e};
+}
+__device__ inline dd dd_add(dd a, dd b) {
+    dd s = two_sum(a.hi, b.hi);
+    dd t = two_sum(a.lo, b.lo);
+    s.lo += t.hi;
+    s = quick_two_sum(s.hi, s.lo);
+    s.lo += t.lo;
+    return quick_two_sum(s.hi, s.lo);
+}
+__device__ inline dd dd_neg(dd a) { return {-a.hi, -a.lo}; }
+__device__ inline dd dd_sub(dd a, dd b) { return dd_add(a, dd_neg(b)); }
+__device__ inline dd dd_mul(dd a, dd b) {
+    dd p = two_prod(a.hi, b.hi);
+    p.lo += a.hi * b.lo;
+    p.lo += a.lo * b.hi;
+    return quick_two_sum(p.hi, p.lo);
+}
+__device__ inline dd dd_mul_d(dd a, double b) {
+    dd p = two_prod(a.hi, b);
+    p.lo += a.lo * b;
+    return quick_two_sum(p.hi, p.lo);
+}
+__device__ inline dd dd_div(dd a, dd b) {
+    // long division: two quotient digits and a correction
+    double q1 = a.hi / b.hi;
+    dd r = dd_sub(a, dd_mul_d(b, q1));
+    double q2 = r.hi / b.hi;
+    r = dd_sub(r, dd_mul_d(b, q2));
+    double q3 = r.hi / b.hi;
+    dd q = quick_two_sum(q1, q2);
+    return dd_add(q, dd{q3, 0.0});
+}
+#pragma clang fp contract(on)
+
+// ln(m) for m in [sqrt(1/2), sqrt(2)]: 2 atanh(u), u = (m - 1) / (m + 1),
+// |u| <= 0.1716, summed as u * sum_k u^(2k) / (2k + 1) for k < 24; u^2 < 2^-5.08,
+// so the truncated tail is below 2^-120 of the sum. coef[k] = 1 / (2k + 1) in double-double.
+constexpr int kLnTerms = 24;
+
+__device__ inline dd dd_ln_reduced(dd m, const dd *coef) {
+    dd num = dd_sub(m, dd{1.0, 0.0});
+    dd den = dd_add(m, dd{1.0, 0.0});
+    dd u = dd_div(num, den);
+    dd w = dd_mul(u, u);
+    dd acc = coef[kLnTerms - 1];
+    for (int k = kLnTerms - 2; k >= 0; --k) acc = dd_add(dd_mul(acc, w), coef[k]);
+    dd r = dd_mul(u, acc);
+    return dd{2.0 * r.hi, 2.0 * r.lo};
+}
+
+// ln(x) for an integer-valued double 1 <= x < 2^53: x = m 2^e with m in
+// [sqrt(1/2), sqrt(2)), then ln x = e ln2 + ln m (ln2 passed in).
+__device__ inline dd dd_ln_int(double x, dd ln2, const dd *coef) {
+    int e;
+    double m = __builtin_frexp(x, &e);        // x = m 2^e, m in [0.5, 1)
+    m *= 2.0;
+    e -= 1;                                   // m in [1, 2)
+    if (m > 1.4142135623730951) { m *= 0.5; e += 1; }
+    dd lm = dd_ln_reduced(dd{m, 0.0}, coef);
+    return dd_add(dd_mul_d(ln2, (double)e), lm);
+}
+
+// ---------------------------------------------------------------------------
+// Value storage conversions, round to nearest, ties to even, from FP64.
+// ---------------------------------------------------------------------------
+__device__ inline uint16_t bf16_from_f64(double d) {
+    uint64_t u = __double_as_longlong(d);
+    uint16_t sign = (uint16_t)((u >> 48) & 0x8000u);
+    uint64_t a = u & 0x7fffffffffffffffull;
+    if (a > 0x7ff0000000000000ull) return sign | 0x7fc0u;          // NaN
+    if (a == 0x7ff0000000000000ull) return sign | 0x7f80u;         // infinity
+    int e = (int)(a >> 52) - 1023;                                 // unbiased exponent
+    if (e < -134) return sign;                                     // below half the least subnormal
+    uint64_t m = (a & 0x000fffffffffffffull) | 0x0010000000000000ull;  // value = m 2^(e-52)
+    int qexp = e >= -126 ? e - 7 : -133;                           // BF16 spacing at this value
+    int shift = qexp - (e - 52);                                   // 45 .. 53
+    uint64_t kept = m >> shift;
+    uint64_t rem = m & ((1ull << shift) - 1);
+    uint64_t half = 1ull << (shift - 1);
+    if (rem > half || (rem == half && (kept & 1))) ++kept;
+    if (qexp == -133) return sign | (uint16_t)kept;                // subnormal (kept <= 128)
+    // normal: kept in [128, 256]; a carry to 256 moves into the exponent
+    uint32_t bits = ((uint32_t)(e + 127) << 7) + (uint32_t)(kept - 128);
+    if (bits >= 0x7f80u) return sign | 0x7f80u;                    // overflow
+    return sign | (uint16_t)bits;
+}
+
+__device__ inline float bf16_to_f32(uint16_t b) {
+    return __uint_as_float((uint32_t)b << 16);
+}
+
+}  // namespace mxe

@@ -1,0 +1,151 @@
+// Internal interfaces between the host runtime (api.cpp, serve.cpp) and the
+// HIP kernels. Nothing here is part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace mxe {
+
+// ---- generic -------------------------------------------------------------
+hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s);
+hipError_t launch_iota_i32(int32_t *p, int64_t n, hipStream_t s);
+
+// Exclusive scan of n int32 values (in may equal out). The running total
+// must stay below 2^31. Workspace: scan_ws_bytes(n).
+size_t scan_ws_bytes(int64_t n);
+hipError_t launch_exclusive_scan(const int32_t *in, int32_t *out, int64_t n, void *ws,
+                                 hipStream_t s);
+
+// ---- random permutation (keys + bucket sort) ------------------------------
+// perm: new-to-old, inv: old-to-new. Workspace: random_perm_ws_bytes(n).
+size_t random_perm_ws_bytes(int64_t n);
+hipError_t launch_random_perm(int64_t n, uint64_t stream_seed, int32_t *perm, int32_t *inv,
+                              void *ws, hipStream_t s);
+
+// ---- permuted CSR --------------------------------------------------------
+// rp_b[i'] = exclusive prefix of A's row lengths taken in rperm order.
+// Workspace: permuted_row_ptr_ws_bytes(nrows).
+size_t permuted_row_ptr_ws_bytes(int32_t nrows);
+hipError_t launch_permuted_row_ptr(int32_t nrows, const int32_t *rp, const int32_t *rperm,
+                                   int32_t *rp_b, void *ws, hipStream_t s);
+// Row i' of B <- row rperm[i'] of A with column j -> cinv[j] (cinv may be
+// NULL: no column permutation), re-sorted by new column. val_bytes: 8, 4, 2.
+hipError_t launch_gather_relabel_sort(int32_t nrows, const int32_t *rp, const int32_t *col,
+                                      const void *val, int val_bytes, const int32_t *rperm,
+                                      const int32_t *cinv, const int32_t *rp_b, int32_t *col_b,
+                                      void *val_b, hipStream_t s);
+
+// ---- vectors --------------------------------------------------------------
+// elem_bytes 8 (FP64) or 4 (FP32).
+hipError_t launch_gather_rows(int32_t n, int32_t k, const int32_t *perm, const void *X,
+                              int64_t ldx, void *Xp, int64_t ldxp, int elem_bytes, hipStream_t s);
+hipError_t launch_scatter_rows(int32_t n, int32_t k, const int32_t *perm, const void *Yp,
+                               int64_t ldyp, void *Y, int64_t ldy, int elem_bytes, hipStream_t s);
+
+// ---- values ----------------------------------------------------------------
+hipError_t launch_convert_f64(const double *in, void *out, int64_t n, int dtype, hipStream_t s);
+
+// ---- row statistics and length bins --------------------------------------
+constexpr int kNumBins = 7;              // lanes per row 1, 2, 4, ..., 64
+// Writes the longest row length to *max_len (device int32).
+hipError_t launch_row_max(int32_t nrows, const int32_t *rp, int32_t *max_len, hipStream_t s);
+// Stable partition of the rows by length bin: rows with bin b fill
+// list[bin_off[b] .. bin_off[b+1]) in increasing order. bin_off (device,
+// kNumBins + 1 int32). Workspace: row_bins_ws_bytes(nrows).
+size_t row_bins_ws_bytes(int32_t nrows);
+hipError_t launch_row_bins(int32_t nrows, const int32_t *rp, int32_t *list, int32_t *bin_off,
+                           void *ws, hipStream_t s);
+// lanes for a row of length len in the binned variant
+__host__ __device__ inline int bin_of_length(int32_t len) {
+    int b = 0;
+    while (b < kNumBins - 1 && len > (2 << b)) ++b;   // <=2: 1 lane, <=4: 2, ..., >64: 64
+    return b;
+}
+
+// ---- histogram and entropy -------------------------------------------------
+// hist: grid_r * grid_c uint32 (device). Workspace: block_hist_ws_bytes().
+hipError_t launch_block_hist(int32_t nrows, int32_t ncols, int64_t nnz, const int32_t *rp,
+                             const int32_t *col, int32_t grid_r, int32_t grid_c, uint32_t *hist,
+                             hipStream_t s);
+// result (device, 4 doubles): h_bits, h_nats, certified (1.0 / 0.0), S.
+size_t entropy_ws_bytes(int64_t bins);
+hipError_t launch_entropy(const uint32_t *hist, int64_t bins, double *result, void *ws,
+                          hipStream_t s);
+
+// ---- SpMV / SpMM ------------------------------------------------------------
+enum ValType { VAL_F64 = 0, VAL_F32 = 1, VAL_BF16 = 2 };
+
+// Column-slab layout (kernels_slab.hip): geometry for one right-hand-side class.
+struct SlabGeom {
+    int32_t nrows, ncols;
+    int32_t slabs, width, cbits;          // column slabs of `width` columns
+    int32_t rows_per_block, rows_per_sub; // workgroup block, wavefront sub-block
+    int32_t blocks, kclass;
+};
+// false when the matrix cannot use the layout (packed indices would not fit)
+bool slab_geometry(int32_t nrows, int32_t ncols, int kclass, int vtype, int cu_count,
+                   int64_t slab_bytes, SlabGeom *g);
+size_t slab_offsets_count(const SlabGeom &g);
+size_t slab_build_ws_bytes(const SlabGeom &g);
+hipError_t launch_slab_build(const SlabGeom &g, const int32_t *rp, const int32_t *col,
+                             const void *val, int val_bytes, int32_t *off, uint32_t *idx_out,
+                             void *val_out, void *ws, hipStream_t s);
+hipError_t launch_spmv_slab(const SlabGeom &g, int vtype, const int32_t *off, const uint32_t *idx,
+                            const void *val, int32_t k, const void *X, int64_t ldx, void *Y,
+                            int64_t ldy, hipStream_t s);
+
+struct SpmvArgs {
+    int32_t nrows, ncols;
+    int64_t nnz;
+    const int32_t *rp, *col;
+    const void *val;
+    int vtype;                 // ValType; X/Y are FP64 for VAL_F64 else FP32
+    int32_t k;
+    const void *X;
+    int64_t ldx;
+    void *Y;
+    int64_t ldy;
+    // binned variant
+    const int32_t *bin_list;
+    const int32_t *bin_off_host;   // kNumBins + 1 host ints
+    // merge variant workspace (merge_ws_bytes)
+    void *merge_ws;
+    // slab variant layout (null when not built)
+    const SlabGeom *slab;
+    const int32_t *slab_off;
+    const uint32_t *slab_idx;
+    const void *slab_val;
+};
+
+size_t merge_ws_bytes(int32_t nrows, int64_t nnz);
+// variant: MXE_VARIANT(family, lanes) as in mxe.h
+hipError_t launch_spmv(const SpmvArgs &a, int variant, hipStream_t s);
+
+// ---- batched persistent SpMV ------------------------------------------------
+struct BatchDesc {             // one matrix of a batch (device-resident table)
+    const int32_t *rp, *col;
+    const void *val;
+    const void *X;
+    void *Y;
+    int64_t ldx, ldy;
+    int32_t nrows, k;
+    int32_t vtype, lanes;      // lanes per row (1..64)
+    int32_t rows_per_tile;     // rows one work item covers
+    int32_t tile_begin;        // first global tile index of this matrix
+};
+// descs: device table of count entries; counter: device int32 zeroed by
+// launch_batch_reset before each launch. total_tiles = sum of tiles.
+hipError_t launch_batch_reset(int32_t *counter, hipStream_t s);
+hipError_t launch_spmv_batch(const BatchDesc *descs, int32_t count, int32_t total_tiles,
+                             int32_t *counter, int32_t grid, hipStream_t s);
+int32_t batch_grid_size();
+
+// ---- serving: pack / unpack merged right-hand sides -------------------------
+// Copies k columns between a caller matrix (ld) and columns [c0, c0+k) of a
+// packed matrix (ldp); elem_bytes 8 or 4.
+hipError_t launch_copy_cols(int32_t n, int32_t k, const void *src, int64_t lds, void *dst,
+                            int64_t ldd, int elem_bytes, hipStream_t s);
+
+}  // namespace mxe

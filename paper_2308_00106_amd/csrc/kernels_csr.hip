@@ -1,0 +1,553 @@
+// Random permutation, permuted CSR construction, vector permutes, scans,
+// row-length bins and value conversion for gfx950 (wave64).
+//
+// The random permutation (Section 3; Eq. 1) is the stable ascending order of
+// 64-bit SplitMix64 keys. Because the keys are a pure function of the index,
+// they are never stored: a most-significant-digit bucket pass splits the
+// index range by the top b key bits (b chosen so a bucket holds ~30 items),
+// and one wavefront per bucket then ranks its items by (key, index) in
+// registers. Two light passes over 4-byte indices replace the eight
+// read-write passes of an LSD radix sort over 12-byte (key, index) pairs.
+#include "device_common.h"
+#include "internal.h"
+
+namespace mxe {
+
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kScanItems = 8;                          // per thread
+constexpr int kScanTile = kBlock * kScanItems;         // 2048 per workgroup
+
+inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+inline size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+inline int grid_for(int64_t n, int per_block = kBlock, int64_t cap = 1 << 20) {
+    int64_t g = cdiv(n, per_block);
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (int)g;
+}
+
+// ---- fills -------------------------------------------------------------------
+
+__global__ void k_fill_i32(int32_t *p, int64_t n, int32_t v) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+__global__ void k_iota_i32(int32_t *p, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = (int32_t)i;
+}
+
+// ---- block-level exclusive scan of one int per thread ----------------------
+
+__device__ inline int32_t block_exclusive_scan(int32_t v, int32_t *wsum, int32_t *total) {
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    int32_t inc = v;
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+        int32_t t = __shfl_up(inc, off);
+        if (lane >= off) inc += t;
+    }
+    if (lane == kWave - 1) wsum[wave] = inc;
+    __syncthreads();
+    int32_t woff = 0, tot = 0;
+    for (int w = 0; w < kBlock / kWave; ++w) {
+        if (w < wave) woff += wsum[w];
+        tot += wsum[w];
+    }
+    __syncthreads();
+    if (total) *total = tot;
+    return inc - v + woff;
+}
+
+// ---- three-phase exclusive scan ---------------------------------------------
+
+__global__ __launch_bounds__(kBlock) void k_scan_tile_sums(const int32_t *in, int64_t n,
+                                                           int32_t *sums) {
+    __shared__ int32_t wsum[kBlock / kWave];
+    int64_t base = (int64_t)blockIdx.x * kScanTile;
+    int32_t acc = 0;
+#pragma unroll
+    for (int t = 0; t < kScanItems; ++t) {
+        int64_t i = base + t * kBlock + threadIdx.x;
+        if (i < n) acc += in[i];
+    }
+    int32_t tot;
+    block_exclusive_scan(acc, wsum, &tot);
+    if (threadIdx.x == 0) sums[blockIdx.x] = tot;
+}
+
+// One workgroup scans the tile sums in place (exclusive).
+__global__ __launch_bounds__(kBlock) void k_scan_sums(int32_t *sums, int64_t ntiles) {
+    __shared__ int32_t wsum[kBlock / kWave];
+    int32_t carry = 0;
+    for (int64_t base = 0; base < ntiles; base += kBlock) {
+        int64_t i = base + threadIdx.x;
+        int32_t v = i < ntiles ? sums[i] : 0;
+        int32_t tot;
+        int32_t ex = block_exclusive_scan(v, wsum, &tot);
+        if (i < ntiles) sums[i] = carry + ex;
+        carry += tot;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_scan_tiles(const int32_t *in, int32_t *out,
+                                                       int64_t n, const int32_t *sums) {
+    __shared__ int32_t tile[kScanTile];
+    __shared__ int32_t wsum[kBlock / kWave];
+    int64_t base = (int64_t)blockIdx.x * kScanTile;
+#pragma unroll
+    for (int t = 0; t < kScanItems; ++t) {
+        int64_t i = base + t * kBlock + threadIdx.x;
+        tile[t * kBlock + threadIdx.x] = i < n ? in[i] : 0;
+    }
+    __syncthreads();
+    int32_t loc[kScanItems];
+    int32_t acc = 0;
+#pragma unroll
+    for (int t = 0; t < kScanItems; ++t) {
+        loc[t] = acc;
+        acc += tile[threadIdx.x * kScanItems + t];
+    }
+    int32_t ex = block_exclusive_scan(acc, wsum, nullptr) + sums[blockIdx.x];
+#pragma unroll
+    for (int t = 0; t < kScanItems; ++t) tile[threadIdx.x * kScanItems + t] = loc[t] + ex;
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < kScanItems; ++t) {
+        int64_t i = base + t * kBlock + threadIdx.x;
+        if (i < n) out[i] = tile[t * kBlock + threadIdx.x];
+    }
+}
+
+// ---- random permutation ------------------------------------------------------
+
+inline int bucket_bits(int64_t n) {
+    int b = 0;
+    while (b < 20 && (n >> b) > 48) ++b;     // mean bucket size in (24, 48]
+    return b;
+}
+
+__device__ inline uint32_t bucket_of(uint64_t key, int bits) {
+    return bits == 0 ? 0u : (uint32_t)(key >> (64 - bits));
+}
+
+__global__ __launch_bounds__(kBlock) void k_bucket_count(int64_t n, uint64_t seed, int bits,
+                                                         int32_t *counts, int32_t *slot) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        uint32_t b = bucket_of(sm64_key(seed, (uint64_t)i), bits);
+        slot[i] = atomicAdd(&counts[b], 1);
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_bucket_scatter(int64_t n, uint64_t seed, int bits,
+                                                           const int32_t *offsets,
+                                                           const int32_t *slot, int32_t *items) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        uint32_t b = bucket_of(sm64_key(seed, (uint64_t)i), bits);
+        items[offsets[b] + slot[i]] = (int32_t)i;
+    }
+}
+
+__device__ inline uint64_t readlane_u64(uint64_t v, int lane) {
+    uint32_t lo = __builtin_amdgcn_readlane((int)(uint32_t)v, lane);
+    uint32_t hi = __builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), lane);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// One wavefront per bucket: each item's final position is the bucket offset
+// plus the number of bucket items ordered before it by (key, index).
+__global__ __launch_bounds__(kBlock) void k_bucket_rank(int64_t nbuckets, uint64_t seed,
+                                                        const int32_t *offsets,
+                                                        const int32_t *items, int32_t *perm,
+                                                        int32_t *inv) {
+    const int lane = threadIdx.x & (kWave - 1);
+    int64_t bucket = (int64_t)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
+    if (bucket >= nbuckets) return;                      // uniform per wavefront
+    const int32_t o = offsets[bucket];
+    const int32_t m = offsets[bucket + 1] - o;
+    for (int32_t c0 = 0; c0 < m; c0 += kWave) {
+        const bool valid = c0 + lane < m;
+        const int32_t idx = valid ? items[o + c0 + lane] : 0x7fffffff;
+        const uint64_t key = valid ? sm64_key(seed, (uint64_t)idx) : ~0ull;
+        int32_t rank = 0;
+        for (int32_t d0 = 0; d0 < m; d0 += kWave) {
+            const bool ov = d0 + lane < m;
+            const int32_t oidx = ov ? items[o + d0 + lane] : 0;
+            const uint64_t okey = ov ? sm64_key(seed, (uint64_t)oidx) : 0;
+            const int cnt = min(kWave, m - d0);
+            for (int j = 0; j < cnt; ++j) {
+                uint64_t kj = readlane_u64(okey, j);
+                int32_t ij = __builtin_amdgcn_readlane(oidx, j);
+                rank += (kj < key) | ((kj == key) & (ij < idx));
+            }
+        }
+        if (valid) {
+            perm[o + rank] = idx;
+            inv[idx] = o + rank;
+        }
+    }
+}
+
+// ---- permuted CSR --------------------------------------------------------------
+
+__global__ __launch_bounds__(kBlock) void k_perm_row_len(int32_t nrows, const int32_t *rp,
+                                                         const int32_t *rperm, int32_t *len) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < nrows) {
+        int32_t src = rperm[i];
+        len[i] = rp[src + 1] - rp[src];
+    } else if (i == nrows) {
+        len[i] = 0;
+    }
+}
+
+constexpr int kSortGroup = 16;                          // lanes per row
+constexpr int kSortRows = kBlock / kSortGroup;          // rows per workgroup step
+constexpr int kSortCap = 256;                           // columns staged in LDS per row
+
+// Each group of 16 lanes moves one row: relabels its columns through cinv,
+// stages them in LDS, and places every entry at its rank among the row's new
+// columns (distinct, so the rank is its sorted position). Rows longer than the
+// LDS stage read the relabelled columns straight from memory.
+template <typename V>
+__global__ __launch_bounds__(kBlock) void k_gather_relabel_sort(
+    int32_t nrows, const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
+    const V *__restrict__ val, const int32_t *__restrict__ rperm, const int32_t *__restrict__ cinv,
+    const int32_t *__restrict__ rp_b, int32_t *__restrict__ col_b, V *__restrict__ val_b) {
+    __shared__ int32_t stage[kSortRows][kSortCap];
+    const int g = threadIdx.x / kSortGroup, t0 = threadIdx.x % kSortGroup;
+    for (int64_t base = (int64_t)blockIdx.x * kSortRows; base < nrows;
+         base += (int64_t)gridDim.x * kSortRows) {
+        const int64_t row = base + g;
+        int32_t s0 = 0, len = 0, d0 = 0;
+        if (row < nrows) {
+            const int32_t src = rperm[row];
+            s0 = rp[src];
+            len = rp[src + 1] - s0;
+            d0 = rp_b[row];
+        }
+        if (cinv == nullptr) {                          // rows only: order unchanged
+            for (int32_t t = t0; t < len; t += kSortGroup) {
+                col_b[d0 + t] = col[s0 + t];
+                val_b[d0 + t] = val[s0 + t];
+            }
+            continue;
+        }
+        const bool staged = len <= kSortCap;
+        if (staged)
+            for (int32_t t = t0; t < len; t += kSortGroup) stage[g][t] = cinv[col[s0 + t]];
+        __syncthreads();
+        for (int32_t t = t0; t < len; t += kSortGroup) {
+            const int32_t c = staged ? stage[g][t] : cinv[col[s0 + t]];
+            int32_t r = 0;
+            if (staged) {
+                for (int32_t u = 0; u < len; ++u) r += stage[g][u] < c;
+            } else {
+                for (int32_t u = 0; u < len; ++u) r += cinv[col[s0 + u]] < c;
+            }
+            col_b[d0 + r] = c;
+            val_b[d0 + r] = val[s0 + t];
+        }
+        __syncthreads();
+    }
+}
+
+// ---- vector permutes (Eq. 1) -----------------------------------------------------
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_gather_rows(int32_t n, int32_t k,
+                                                        const int32_t *__restrict__ perm,
+                                                        const T *__restrict__ X, int64_t ldx,
+                                                        T *__restrict__ Xp, int64_t ldxp) {
+    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n;
+         j += (int64_t)gridDim.x * blockDim.x) {
+        const T *src = X + (int64_t)perm[j] * ldx;
+        T *dst = Xp + j * ldxp;
+        for (int32_t c = 0; c < k; ++c) dst[c] = src[c];
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_scatter_rows(int32_t n, int32_t k,
+                                                         const int32_t *__restrict__ perm,
+                                                         const T *__restrict__ Yp, int64_t ldyp,
+                                                         T *__restrict__ Y, int64_t ldy) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const T *src = Yp + i * ldyp;
+        T *dst = Y + (int64_t)perm[i] * ldy;
+        for (int32_t c = 0; c < k; ++c) dst[c] = src[c];
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_copy_cols(int32_t n, int32_t k, const T *__restrict__ src,
+                                                      int64_t lds, T *__restrict__ dst,
+                                                      int64_t ldd) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        for (int32_t c = 0; c < k; ++c) dst[i * ldd + c] = src[i * lds + c];
+}
+
+// ---- value conversion --------------------------------------------------------------
+
+__global__ __launch_bounds__(kBlock) void k_f64_to_f32(const double *in, float *out, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = (float)in[i];                 // v_cvt_f32_f64: round to nearest even
+}
+
+__global__ __launch_bounds__(kBlock) void k_f64_to_bf16(const double *in, uint16_t *out,
+                                                        int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = bf16_from_f64(in[i]);
+}
+
+// ---- row statistics and bins ------------------------------------------------------
+
+__global__ __launch_bounds__(kBlock) void k_row_max(int32_t nrows, const int32_t *rp,
+                                                    int32_t *max_len) {
+    int32_t m = 0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nrows;
+         i += (int64_t)gridDim.x * blockDim.x)
+        m = max(m, rp[i + 1] - rp[i]);
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) m = max(m, __shfl_xor(m, off));
+    if ((threadIdx.x & (kWave - 1)) == 0) atomicMax(max_len, m);
+}
+
+__global__ __launch_bounds__(kBlock) void k_bin_count(int32_t nrows, const int32_t *rp,
+                                                      int32_t *cnt, int32_t nwg) {
+    __shared__ int32_t c[kNumBins];
+    if (threadIdx.x < kNumBins) c[threadIdx.x] = 0;
+    __syncthreads();
+    int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (r < nrows) atomicAdd(&c[bin_of_length(rp[r + 1] - rp[r])], 1);
+    __syncthreads();
+    if (threadIdx.x < kNumBins) cnt[(int64_t)threadIdx.x * nwg + blockIdx.x] = c[threadIdx.x];
+}
+
+__global__ __launch_bounds__(kBlock) void k_bin_scatter(int32_t nrows, const int32_t *rp,
+                                                        const int32_t *off, int32_t nwg,
+                                                        int32_t *list) {
+    __shared__ int32_t wc[kBlock / kWave][kNumBins];
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int b = r < nrows ? bin_of_length(rp[r + 1] - rp[r]) : -1;
+    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (kWave - lane));
+    int my_rank = 0;
+    for (int q = 0; q < kNumBins; ++q) {
+        uint64_t m = __ballot(b == q);
+        if (b == q) my_rank = __popcll(m & lt);
+        if (lane == 0) wc[wave][q] = __popcll(m);
+    }
+    __syncthreads();
+    if (b >= 0) {
+        int32_t pos = off[(int64_t)b * nwg + blockIdx.x] + my_rank;
+        for (int w = 0; w < wave; ++w) pos += wc[w][b];
+        list[pos] = (int32_t)r;
+    }
+}
+
+__global__ void k_bin_bounds(const int32_t *off, int32_t nwg, int32_t nrows, int32_t *bin_off) {
+    int b = threadIdx.x;
+    if (b < kNumBins) bin_off[b] = off[(int64_t)b * nwg];
+    if (b == kNumBins) bin_off[b] = nrows;
+}
+
+}  // namespace
+
+// ============================ launchers ==========================================
+
+hipError_t launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(n, kBlock, 4096)), dim3(kBlock), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_iota_i32(int32_t *p, int64_t n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_iota_i32, dim3(grid_for(n, kBlock, 4096)), dim3(kBlock), 0, s, p, n);
+    return hipGetLastError();
+}
+
+size_t scan_ws_bytes(int64_t n) { return align256(sizeof(int32_t) * (size_t)(cdiv(n, kScanTile) + 1)); }
+
+hipError_t launch_exclusive_scan(const int32_t *in, int32_t *out, int64_t n, void *ws,
+                                 hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    int64_t ntiles = cdiv(n, kScanTile);
+    int32_t *sums = (int32_t *)ws;
+    hipLaunchKernelGGL(k_scan_tile_sums, dim3(ntiles), dim3(kBlock), 0, s, in, n, sums);
+    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(kBlock), 0, s, sums, ntiles);
+    hipLaunchKernelGGL(k_scan_tiles, dim3(ntiles), dim3(kBlock), 0, s, in, out, n,
+                       (const int32_t *)sums);
+    return hipGetLastError();
+}
+
+size_t random_perm_ws_bytes(int64_t n) {
+    int64_t nb = int64_t(1) << bucket_bits(n);
+    return align256(sizeof(int32_t) * (nb + 1)) + 2 * align256(sizeof(int32_t) * (n + 1)) +
+           scan_ws_bytes(nb + 1);
+}
+
+hipError_t launch_random_perm(int64_t n, uint64_t stream_seed, int32_t *perm, int32_t *inv,
+                              void *ws, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const int bits = bucket_bits(n);
+    const int64_t nb = int64_t(1) << bits;
+    char *w = (char *)ws;
+    int32_t *counts = (int32_t *)w;  w += align256(sizeof(int32_t) * (nb + 1));
+    int32_t *slot = (int32_t *)w;    w += align256(sizeof(int32_t) * (n + 1));
+    int32_t *items = (int32_t *)w;   w += align256(sizeof(int32_t) * (n + 1));
+    void *scan_ws = w;
+    hipError_t e = launch_fill_i32(counts, nb + 1, 0, s);
+    if (e != hipSuccess) return e;
+    const int g = grid_for(n, kBlock, 8192);
+    hipLaunchKernelGGL(k_bucket_count, dim3(g), dim3(kBlock), 0, s, n, stream_seed, bits, counts,
+                       slot);
+    e = launch_exclusive_scan(counts, counts, nb + 1, scan_ws, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_bucket_scatter, dim3(g), dim3(kBlock), 0, s, n, stream_seed, bits,
+                       (const int32_t *)counts, (const int32_t *)slot, items);
+    hipLaunchKernelGGL(k_bucket_rank, dim3(cdiv(nb, kBlock / kWave)), dim3(kBlock), 0, s, nb,
+                       stream_seed, (const int32_t *)counts, (const int32_t *)items, perm, inv);
+    return hipGetLastError();
+}
+
+size_t permuted_row_ptr_ws_bytes(int32_t nrows) { return scan_ws_bytes((int64_t)nrows + 1); }
+
+hipError_t launch_permuted_row_ptr(int32_t nrows, const int32_t *rp, const int32_t *rperm,
+                                   int32_t *rp_b, void *ws, hipStream_t s) {
+    hipLaunchKernelGGL(k_perm_row_len, dim3(grid_for((int64_t)nrows + 1, kBlock, 1 << 30)),
+                       dim3(kBlock), 0, s, nrows, rp, rperm, rp_b);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_exclusive_scan(rp_b, rp_b, (int64_t)nrows + 1, ws, s);
+}
+
+hipError_t launch_gather_relabel_sort(int32_t nrows, const int32_t *rp, const int32_t *col,
+                                      const void *val, int val_bytes, const int32_t *rperm,
+                                      const int32_t *cinv, const int32_t *rp_b, int32_t *col_b,
+                                      void *val_b, hipStream_t s) {
+    if (nrows <= 0) return hipSuccess;
+    const int g = grid_for(nrows, kSortRows, 16384);
+    switch (val_bytes) {
+    case 8:
+        hipLaunchKernelGGL(k_gather_relabel_sort<uint64_t>, dim3(g), dim3(kBlock), 0, s, nrows, rp,
+                           col, (const uint64_t *)val, rperm, cinv, rp_b, col_b, (uint64_t *)val_b);
+        break;
+    case 4:
+        hipLaunchKernelGGL(k_gather_relabel_sort<uint32_t>, dim3(g), dim3(kBlock), 0, s, nrows, rp,
+                           col, (const uint32_t *)val, rperm, cinv, rp_b, col_b, (uint32_t *)val_b);
+        break;
+    case 2:
+        hipLaunchKernelGGL(k_gather_relabel_sort<uint16_t>, dim3(g), dim3(kBlock), 0, s, nrows, rp,
+                           col, (const uint16_t *)val, rperm, cinv, rp_b, col_b, (uint16_t *)val_b);
+        break;
+    default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_rows(int32_t n, int32_t k, const int32_t *perm, const void *X,
+                              int64_t ldx, void *Xp, int64_t ldxp, int elem_bytes, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const int g = grid_for(n, kBlock, 16384);
+    if (elem_bytes == 8)
+        hipLaunchKernelGGL(k_gather_rows<double>, dim3(g), dim3(kBlock), 0, s, n, k, perm,
+                           (const double *)X, ldx, (double *)Xp, ldxp);
+    else if (elem_bytes == 4)
+        hipLaunchKernelGGL(k_gather_rows<float>, dim3(g), dim3(kBlock), 0, s, n, k, perm,
+                           (const float *)X, ldx, (float *)Xp, ldxp);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_scatter_rows(int32_t n, int32_t k, const int32_t *perm, const void *Yp,
+                               int64_t ldyp, void *Y, int64_t ldy, int elem_bytes, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const int g = grid_for(n, kBlock, 16384);
+    if (elem_bytes == 8)
+        hipLaunchKernelGGL(k_scatter_rows<double>, dim3(g), dim3(kBlock), 0, s, n, k, perm,
+                           (const double *)Yp, ldyp, (double *)Y, ldy);
+    else if (elem_bytes == 4)
+        hipLaunchKernelGGL(k_scatter_rows<float>, dim3(g), dim3(kBlock), 0, s, n, k, perm,
+                           (const float *)Yp, ldyp, (float *)Y, ldy);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_cols(int32_t n, int32_t k, const void *src, int64_t lds, void *dst,
+                            int64_t ldd, int elem_bytes, hipStream_t s) {
+    if (n <= 0 || k <= 0) return hipSuccess;
+    const int g = grid_for(n, kBlock, 16384);
+    if (elem_bytes == 8)
+        hipLaunchKernelGGL(k_copy_cols<double>, dim3(g), dim3(kBlock), 0, s, n, k,
+                           (const double *)src, lds, (double *)dst, ldd);
+    else if (elem_bytes == 4)
+        hipLaunchKernelGGL(k_copy_cols<float>, dim3(g), dim3(kBlock), 0, s, n, k,
+                           (const float *)src, lds, (float *)dst, ldd);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_convert_f64(const double *in, void *out, int64_t n, int dtype, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const int g = grid_for(n, kBlock, 16384);
+    if (dtype == VAL_F32)
+        hipLaunchKernelGGL(k_f64_to_f32, dim3(g), dim3(kBlock), 0, s, in, (float *)out, n);
+    else if (dtype == VAL_BF16)
+        hipLaunchKernelGGL(k_f64_to_bf16, dim3(g), dim3(kBlock), 0, s, in, (uint16_t *)out, n);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_row_max(int32_t nrows, const int32_t *rp, int32_t *max_len, hipStream_t s) {
+    hipError_t e = launch_fill_i32(max_len, 1, 0, s);
+    if (e != hipSuccess || nrows <= 0) return e;
+    hipLaunchKernelGGL(k_row_max, dim3(grid_for(nrows, kBlock, 2048)), dim3(kBlock), 0, s, nrows,
+                       rp, max_len);
+    return hipGetLastError();
+}
+
+size_t row_bins_ws_bytes(int32_t nrows) {
+    int64_t nwg = cdiv(nrows, kBlock);
+    int64_t n = kNumBins * nwg;
+    return align256(sizeof(int32_t) * (n + 1)) + scan_ws_bytes(n);
+}
+
+hipError_t launch_row_bins(int32_t nrows, const int32_t *rp, int32_t *list, int32_t *bin_off,
+                           void *ws, hipStream_t s) {
+    const int32_t nwg = (int32_t)cdiv(nrows, kBlock);
+    if (nrows <= 0) {
+        hipError_t e = launch_fill_i32(bin_off, kNumBins + 1, 0, s);
+        return e;
+    }
+    int32_t *cnt = (int32_t *)ws;
+    void *scan_ws = (char *)ws + align256(sizeof(int32_t) * ((int64_t)kNumBins * nwg + 1));
+    hipLaunchKernelGGL(k_bin_count, dim3(nwg), dim3(kBlock), 0, s, nrows, rp, cnt, nwg);
+    hipError_t e = launch_exclusive_scan(cnt, cnt, (int64_t)kNumBins * nwg, scan_ws, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_bin_scatter, dim3(nwg), dim3(kBlock), 0, s, nrows, rp,
+                       (const int32_t *)cnt, nwg, list);
+    hipLaunchKernelGGL(k_bin_bounds, dim3(1), dim3(kWave), 0, s, (const int32_t *)cnt, nwg, nrows,
+                       bin_off);
+    return hipGetLastError();
+}
+
+}  // namespace mxe

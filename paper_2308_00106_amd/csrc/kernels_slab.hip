@@ -1,0 +1,340 @@
+// Column-slab SpMV for gfx950: the x gathers of a max-entropy matrix made
+// L2-resident.
+//
+// After the random column permutation every row's columns are spread
+// uniformly over x (Section 3's aim), so with x larger than one XCD's 4 MB L2
+// most gathers miss to the Infinity Cache at a full cache line per 8 useful
+// bytes. The paper's custom-hardware answer is a banked x buffer (Section 1);
+// the MI355X counterpart is the per-XCD L2.
+//
+// Layout (built once per matrix and right-hand-side class): columns are cut
+// into S slabs whose x slice fits comfortably in one L2; rows are cut into
+// workgroup blocks of R rows, each split into 16 wavefront sub-blocks. Entries
+// are stored grouped by (block, sub-block, slab), rows ascending inside a
+// group, each as one 32-bit word (row in sub-block << cbits | column in slab)
+// plus its value. The product keeps each block's partial y in LDS and walks
+// the slabs in a rotation that starts at a slab tied to the workgroup's XCD
+// (workgroups are dealt to the 8 XCDs round-robin), so at any moment an XCD's
+// workgroups gather from one slab of x that sits in its L2. Because a
+// max-entropy matrix gives every (block, slab) tile the same expected nonzero
+// count, the workgroups of an XCD stay in step. Each row's sum is taken in a
+// fixed order (slabs in rotation order, entries in storage order, a fixed
+// segmented scan inside a wavefront), so results are deterministic.
+#include "device_common.h"
+#include "internal.h"
+
+#include <algorithm>
+
+namespace mxe {
+
+namespace {
+
+constexpr int kSlabBlock = 1024;                    // 16 wavefronts
+constexpr int kSubBlocks = kSlabBlock / kWave;      // wavefront sub-blocks per block
+constexpr int kSlabMax = 64;                       // column slabs per layout
+// 64-entry chunks each wavefront keeps in flight (fewer for wide right-hand sides)
+template <int KM> struct Unroll { static constexpr int value = KM <= 2 ? 4 : KM <= 4 ? 2 : 1; };
+
+inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+inline int bits_for(int64_t n) {                    // bits to hold 0 .. n-1
+    int b = 0;
+    while ((int64_t(1) << b) < n) ++b;
+    return b;
+}
+
+__device__ inline int32_t slab_of(int32_t col, int32_t width, double inv_w) {
+    int32_t q = (int32_t)((double)col * inv_w);
+    if ((int64_t)q * width > col) --q;
+    else if ((int64_t)(q + 1) * width <= col) ++q;
+    return q;
+}
+
+// Pass 1: entries per (block, sub-block, slab).
+__global__ __launch_bounds__(kSlabBlock) void k_slab_count(SlabGeom g, const int32_t *__restrict__ rp,
+                                                           const int32_t *__restrict__ col,
+                                                           int32_t *__restrict__ cnt) {
+    __shared__ int32_t c[kSubBlocks][kSlabMax];
+    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    for (int s = lane; s < g.slabs; s += kWave) c[wave][s] = 0;
+    __syncthreads();
+    const int64_t r0 = (int64_t)blockIdx.x * g.rows_per_block + (int64_t)wave * g.rows_per_sub;
+    const int64_t r1 = std::min<int64_t>(std::min<int64_t>(r0 + g.rows_per_sub,
+                                         (int64_t)(blockIdx.x + 1) * g.rows_per_block), g.nrows);
+    const double inv_w = 1.0 / g.width;
+    for (int64_t r = r0 + lane; r < r1; r += kWave)
+        for (int32_t e = rp[r]; e < rp[r + 1]; ++e)
+            atomicAdd(&c[wave][slab_of(col[e], g.width, inv_w)], 1);
+    __syncthreads();
+    int32_t *out = cnt + ((int64_t)blockIdx.x * kSubBlocks + wave) * g.slabs;
+    for (int s = lane; s < g.slabs; s += kWave) out[s] = c[wave][s];
+}
+
+// Pass 2: place every entry. Lanes take consecutive rows; for each slab the
+// wavefront scans the per-row counts so rows stay in order inside a group.
+template <typename V>
+__global__ __launch_bounds__(kSlabBlock) void k_slab_fill(SlabGeom g, const int32_t *__restrict__ rp,
+                                                          const int32_t *__restrict__ col,
+                                                          const V *__restrict__ val,
+                                                          const int32_t *__restrict__ off,
+                                                          uint32_t *__restrict__ idx_out,
+                                                          V *__restrict__ val_out) {
+    __shared__ int32_t base[kSubBlocks][kSlabMax];
+    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    const int32_t *o = off + ((int64_t)blockIdx.x * kSubBlocks + wave) * g.slabs;
+    for (int s = lane; s < g.slabs; s += kWave) base[wave][s] = o[s];
+    __syncthreads();
+    const int64_t r0 = (int64_t)blockIdx.x * g.rows_per_block + (int64_t)wave * g.rows_per_sub;
+    const int64_t r1 = std::min<int64_t>(std::min<int64_t>(r0 + g.rows_per_sub,
+                                         (int64_t)(blockIdx.x + 1) * g.rows_per_block), g.nrows);
+    for (int64_t c0 = r0; c0 < r1; c0 += kWave) {          // uniform per wavefront
+        const int64_t r = c0 + lane;
+        int32_t p = 0, end = 0;
+        if (r < r1) {
+            p = rp[r];
+            end = rp[r + 1];
+        }
+        const uint32_t rloc = (uint32_t)(r - r0);
+        for (int s = 0; s < g.slabs; ++s) {
+            const int32_t lim = (int32_t)std::min<int64_t>((int64_t)(s + 1) * g.width, g.ncols);
+            int32_t cnt = 0;
+            while (p + cnt < end && col[p + cnt] < lim) ++cnt;
+            int32_t inc = cnt;                                 // inclusive scan over lanes
+#pragma unroll
+            for (int d = 1; d < kWave; d <<= 1) {
+                int32_t t = __shfl_up(inc, d);
+                if (lane >= d) inc += t;
+            }
+            const int32_t total = __shfl(inc, kWave - 1);
+            const int32_t pos = base[wave][s] + inc - cnt;
+            for (int32_t i = 0; i < cnt; ++i) {
+                idx_out[pos + i] = (rloc << g.cbits) | (uint32_t)col[p + i];
+                val_out[pos + i] = val[p + i];
+            }
+            p += cnt;
+            __builtin_amdgcn_wave_barrier();
+            if (lane == 0) base[wave][s] += total;
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+        }
+    }
+}
+
+template <typename V, typename T> struct SlabVal;
+template <> struct SlabVal<double, double> {
+    __device__ static double get(double v) { return v; }
+};
+template <> struct SlabVal<float, float> {
+    __device__ static float get(float v) { return v; }
+};
+template <> struct SlabVal<uint16_t, float> {
+    __device__ static float get(uint16_t v) { return bf16_to_f32(v); }
+};
+
+// The product. LDS holds the block's partial y (rows_per_block x KM).
+template <typename V, typename T, int KM>
+__global__ __launch_bounds__(kSlabBlock) void k_spmv_slab(SlabGeom g, const int32_t *__restrict__ off,
+                                                          const uint32_t *__restrict__ idx,
+                                                          const V *__restrict__ val, int32_t k,
+                                                          const T *__restrict__ X, int64_t ldx,
+                                                          T *__restrict__ Y, int64_t ldy) {
+    extern __shared__ unsigned char smem[];
+    T *yp = reinterpret_cast<T *>(smem);
+    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    const int32_t R = g.rows_per_block;
+    for (int i = threadIdx.x; i < R * KM; i += kSlabBlock) yp[i] = T(0);
+    __syncthreads();
+    T *ywave = yp + (int64_t)wave * g.rows_per_sub * KM;
+    // This wavefront's groups (one per slab) and their offsets, staged in LDS.
+    __shared__ int32_t soff[kSubBlocks][kSlabMax + 1];
+    const int32_t *o = off + ((int64_t)blockIdx.x * kSubBlocks + wave) * g.slabs;
+    for (int s = lane; s <= g.slabs; s += kWave) soff[wave][s] = o[s];
+    __syncthreads();
+    const int xcd = blockIdx.x % 8;
+    const int s0 = (int)(((int64_t)xcd * g.slabs) / 8);
+    const uint32_t cmask = (1u << g.cbits) - 1u;
+    // Chunk iterator (wavefront-uniform): 64-entry chunks, never straddling a
+    // group, so rows rise monotonically inside every chunk and a row has at
+    // most one segment per chunk. Groups are visited in rotation from s0.
+    int t = 0, s = s0;
+    int32_t c = soff[wave][s0], e = soff[wave][s0 + 1];
+    auto next_chunk = [&](int32_t &start, int32_t &cnt) -> bool {
+        while (c >= e) {
+            if (++t >= g.slabs) return false;
+            s = s0 + t < g.slabs ? s0 + t : s0 + t - g.slabs;
+            c = soff[wave][s];
+            e = soff[wave][s + 1];
+        }
+        start = c;
+        cnt = min(kWave, e - c);
+        c += kWave;
+        return true;
+    };
+    // Software pipeline over kDepth register slots: a slot's index and value
+    // loads are issued kDepth chunks before the slot is reduced.
+    constexpr int kDepth = Unroll<KM>::value;
+    uint32_t u[kDepth];
+    T a[kDepth];
+    bool live[kDepth];
+#pragma unroll
+    for (int j = 0; j < kDepth; ++j) {
+        int32_t st = 0, n = 0;
+        live[j] = next_chunk(st, n);
+        const bool v = live[j] && lane < n;
+        u[j] = v ? __builtin_nontemporal_load(idx + st + lane) : 0xffffffffu;
+        a[j] = v ? SlabVal<V, T>::get(__builtin_nontemporal_load(val + st + lane)) : T(0);
+    }
+    bool more = live[0];
+    while (more) {
+#pragma unroll
+        for (int j = 0; j < kDepth; ++j) {
+            if (!live[j]) {
+                more = false;
+                break;
+            }
+            const bool valid = u[j] != 0xffffffffu;
+            const uint32_t key = valid ? (u[j] >> g.cbits) : 0xffffffffu;
+            const T *xr = X + (int64_t)(valid ? (u[j] & cmask) : 0) * ldx;
+            T prod[KM];
+#pragma unroll
+            for (int q = 0; q < KM; ++q)
+                prod[q] = (valid && (KM == 1 || q < k)) ? a[j] * xr[q] : T(0);
+            {   // refill the slot with the chunk kDepth ahead
+                int32_t st = 0, n = 0;
+                live[j] = next_chunk(st, n);
+                const bool v = live[j] && lane < n;
+                u[j] = v ? __builtin_nontemporal_load(idx + st + lane) : 0xffffffffu;
+                a[j] = v ? SlabVal<V, T>::get(__builtin_nontemporal_load(val + st + lane)) : T(0);
+            }
+            // inclusive segmented scan by row; padding lanes (key 0xffffffff)
+            // sit after every valid lane
+#pragma unroll
+            for (int d = 1; d < kWave; d <<= 1) {
+                const uint32_t kd = __shfl_up(key, d);
+                const bool take = lane >= d && kd == key;
+#pragma unroll
+                for (int q = 0; q < KM; ++q) {
+                    const T v = __shfl_up(prod[q], d);
+                    if (take) prod[q] += v;
+                }
+            }
+            const uint32_t nxt = __shfl_down(key, 1);
+            const bool tail = key != 0xffffffffu && (lane == kWave - 1 || nxt != key);
+            if (tail) {
+#pragma unroll
+                for (int q = 0; q < KM; ++q) ywave[(int64_t)key * KM + q] += prod[q];
+            }
+            // the next chunk's tails may update the same rows: keep order
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+        }
+    }
+    __syncthreads();
+    const int64_t row0 = (int64_t)blockIdx.x * R;
+    for (int i = threadIdx.x; i < R * KM; i += kSlabBlock) {
+        const int64_t row = row0 + i / KM;
+        const int q = i % KM;
+        if (row < g.nrows && (KM == 1 || q < k)) Y[row * ldy + q] = yp[i];
+    }
+}
+
+template <typename V, typename T, int KM>
+hipError_t slab_launch(const SlabGeom &g, const int32_t *off, const uint32_t *idx, const void *val,
+                       int32_t k, const void *X, int64_t ldx, void *Y, int64_t ldy, hipStream_t s) {
+    const size_t lds = (size_t)g.rows_per_block * KM * sizeof(T);
+    hipLaunchKernelGGL((k_spmv_slab<V, T, KM>), dim3(g.blocks), dim3(kSlabBlock), lds, s, g, off,
+                       idx, (const V *)val, k, (const T *)X, ldx, (T *)Y, ldy);
+    return hipGetLastError();
+}
+
+template <typename V, typename T>
+hipError_t slab_by_k(const SlabGeom &g, const int32_t *off, const uint32_t *idx, const void *val,
+                     int32_t k, const void *X, int64_t ldx, void *Y, int64_t ldy, hipStream_t s) {
+    switch (g.kclass) {
+    case 1: return slab_launch<V, T, 1>(g, off, idx, val, k, X, ldx, Y, ldy, s);
+    case 2: return slab_launch<V, T, 2>(g, off, idx, val, k, X, ldx, Y, ldy, s);
+    case 4: return slab_launch<V, T, 4>(g, off, idx, val, k, X, ldx, Y, ldy, s);
+    case 8: return slab_launch<V, T, 8>(g, off, idx, val, k, X, ldx, Y, ldy, s);
+    case 16: return slab_launch<V, T, 16>(g, off, idx, val, k, X, ldx, Y, ldy, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace
+
+bool slab_geometry(int32_t nrows, int32_t ncols, int kclass, int vtype, int cu_count,
+                   int64_t slab_bytes, SlabGeom *g) {
+    if (nrows <= 0 || ncols <= 0) return false;
+    const int64_t xb = vtype == VAL_F64 ? 8 : 4;
+    const int64_t per_col = xb * kclass;
+    int64_t slabs = std::max<int64_t>(1, cdiv((int64_t)ncols * per_col, slab_bytes));
+    if (slabs > kSlabMax) return false;
+    const int64_t width = cdiv(ncols, slabs);
+    slabs = cdiv(ncols, width);
+    // rows per block: two blocks per CU cover the matrix if LDS allows (64 KB each)
+    const int64_t lds_rows = (64 * 1024) / per_col;
+    int64_t R = std::min<int64_t>(cdiv(nrows, 2 * (int64_t)cu_count), lds_rows);
+    R = std::max<int64_t>(R, kSubBlocks);
+    R = cdiv(R, kSubBlocks) * kSubBlocks;
+    // packed words (row in sub-block, global column) stay below 2^31, so they
+    // never equal the padding key; smaller blocks free row bits
+    const int cbits = bits_for(ncols);
+    while (cbits + bits_for(R / kSubBlocks) > 31 && R > kSubBlocks) R = cdiv(R / 2, kSubBlocks) * kSubBlocks;
+    const int64_t Rq = R / kSubBlocks;
+    if (cbits + bits_for(Rq) > 31) return false;
+    g->nrows = nrows;
+    g->ncols = ncols;
+    g->slabs = (int32_t)slabs;
+    g->width = (int32_t)width;
+    g->cbits = cbits;
+    g->rows_per_block = (int32_t)R;
+    g->rows_per_sub = (int32_t)Rq;
+    g->blocks = (int32_t)cdiv(nrows, R);
+    g->kclass = kclass;
+    return true;
+}
+
+size_t slab_offsets_count(const SlabGeom &g) { return (size_t)g.blocks * kSubBlocks * g.slabs + 1; }
+
+size_t slab_build_ws_bytes(const SlabGeom &g) { return scan_ws_bytes((int64_t)slab_offsets_count(g)); }
+
+hipError_t launch_slab_build(const SlabGeom &g, const int32_t *rp, const int32_t *col, const void *val,
+                             int val_bytes, int32_t *off, uint32_t *idx_out, void *val_out, void *ws,
+                             hipStream_t s) {
+    const int64_t n = (int64_t)slab_offsets_count(g);
+    hipError_t e = launch_fill_i32(off, n, 0, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_slab_count, dim3(g.blocks), dim3(kSlabBlock), 0, s, g, rp, col, off);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = launch_exclusive_scan(off, off, n, ws, s)) != hipSuccess) return e;
+    switch (val_bytes) {
+    case 8:
+        hipLaunchKernelGGL(k_slab_fill<uint64_t>, dim3(g.blocks), dim3(kSlabBlock), 0, s, g, rp, col,
+                           (const uint64_t *)val, (const int32_t *)off, idx_out, (uint64_t *)val_out);
+        break;
+    case 4:
+        hipLaunchKernelGGL(k_slab_fill<uint32_t>, dim3(g.blocks), dim3(kSlabBlock), 0, s, g, rp, col,
+                           (const uint32_t *)val, (const int32_t *)off, idx_out, (uint32_t *)val_out);
+        break;
+    case 2:
+        hipLaunchKernelGGL(k_slab_fill<uint16_t>, dim3(g.blocks), dim3(kSlabBlock), 0, s, g, rp, col,
+                           (const uint16_t *)val, (const int32_t *)off, idx_out, (uint16_t *)val_out);
+        break;
+    default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_spmv_slab(const SlabGeom &g, int vtype, const int32_t *off, const uint32_t *idx,
+                            const void *val, int32_t k, const void *X, int64_t ldx, void *Y,
+                            int64_t ldy, hipStream_t s) {
+    if (k > g.kclass) return hipErrorInvalidValue;
+    switch (vtype) {
+    case VAL_F64: return slab_by_k<double, double>(g, off, idx, val, k, X, ldx, Y, ldy, s);
+    case VAL_F32: return slab_by_k<float, float>(g, off, idx, val, k, X, ldx, Y, ldy, s);
+    case VAL_BF16: return slab_by_k<uint16_t, float>(g, off, idx, val, k, X, ldx, Y, ldy, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace mxe

@@ -1,0 +1,462 @@
+// CSR SpMV / SpMM kernels for gfx950 (Section 2: y_i = sum over row i of
+// V[l] * x[COL[l]]), on (+, *) with FP64 accumulation for FP64 storage and
+// FP32 accumulation for FP32 / BF16 storage.
+//
+// The product is bound by HBM bandwidth: each stored entry streams its value
+// and column index once, x is gathered through L2, y is written once. The
+// kernels therefore aim at coalesced val / col streams, enough memory-level
+// parallelism, and keeping x resident in L2 (val, col and row_ptr are loaded
+// non-temporally so the stream does not evict x).
+//
+// Variants (a variant id packs family and lanes per row):
+//   GROUP  L lanes per row (L = 1 ... 64; rows per wavefront = 64 / L), rows
+//          in storage order; lanes stride the row, then a butterfly reduction
+//          over the L lanes.
+//   BINNED rows grouped by length (bins of 1, 2, ... 64 lanes, built once per
+//          matrix), one GROUP launch per non-empty bin over its row list.
+//   MERGE  merge-path split of the row-end / nonzero sequence into equal
+//          slices (Merrill and Garland, SC'16): every workgroup gets the same
+//          work whatever the row lengths; row sums that cross a slice are
+//          carried out and added by a fix-up pass in slice order.
+// Every variant sums each row in a fixed order, so results are deterministic.
+#include "device_common.h"
+#include "internal.h"
+#include "../../include/mxe.h"
+
+#include <algorithm>
+
+namespace mxe {
+
+namespace {
+
+constexpr int kBlock = 256;
+
+inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+template <typename P>
+__device__ inline P ld_stream(const P *p) { return __builtin_nontemporal_load(p); }
+
+template <typename V, typename T> struct ValLoad;
+template <> struct ValLoad<double, double> {
+    __device__ static double get(const double *p) { return ld_stream(p); }
+};
+template <> struct ValLoad<float, float> {
+    __device__ static float get(const float *p) { return ld_stream(p); }
+};
+template <> struct ValLoad<uint16_t, float> {
+    __device__ static float get(const uint16_t *p) { return bf16_to_f32(ld_stream(p)); }
+};
+
+// Accumulate the entries of one row handled by this lane (lane, lane + L, ...),
+// then reduce over the group of L lanes with xor butterflies: every lane ends
+// with the same sum (addition is commutative), in a fixed order.
+template <typename V, typename T, int L, int KM>
+__device__ inline void row_dot(int32_t s, int32_t e, int lane, const int32_t *__restrict__ col,
+                               const V *__restrict__ val, int32_t k, const T *__restrict__ X,
+                               int64_t ldx, T (&acc)[KM]) {
+#pragma unroll
+    for (int q = 0; q < KM; ++q) acc[q] = T(0);
+    int32_t p = s + lane;
+    // two entries in flight per lane
+    for (; p + L < e; p += 2 * L) {
+        const int32_t c0 = ld_stream(col + p), c1 = ld_stream(col + p + L);
+        const T a0 = ValLoad<V, T>::get(val + p), a1 = ValLoad<V, T>::get(val + p + L);
+        const T *x0 = X + (int64_t)c0 * ldx, *x1 = X + (int64_t)c1 * ldx;
+        if (KM == 1) {
+            acc[0] += a0 * x0[0];
+            acc[0] += a1 * x1[0];
+        } else {
+#pragma unroll
+            for (int q = 0; q < KM; ++q)
+                if (q < k) acc[q] += a0 * x0[q];
+#pragma unroll
+            for (int q = 0; q < KM; ++q)
+                if (q < k) acc[q] += a1 * x1[q];
+        }
+    }
+    if (p < e) {
+        const int32_t c0 = ld_stream(col + p);
+        const T a0 = ValLoad<V, T>::get(val + p);
+        const T *x0 = X + (int64_t)c0 * ldx;
+#pragma unroll
+        for (int q = 0; q < KM; ++q)
+            if (KM == 1 || q < k) acc[q] += a0 * x0[q];
+    }
+#pragma unroll
+    for (int off = L / 2; off > 0; off >>= 1)
+#pragma unroll
+        for (int q = 0; q < KM; ++q) acc[q] += __shfl_xor(acc[q], off, L);
+}
+
+template <typename T, int L, int KM>
+__device__ inline void store_row(T *__restrict__ Y, int64_t ldy, int32_t row, int lane, int32_t k,
+                                 const T (&acc)[KM]) {
+    T *y = Y + (int64_t)row * ldy;
+    if (KM == 1) {
+        if (lane == 0) y[0] = acc[0];
+    } else {
+        // spread the k stores over the group's lanes
+#pragma unroll
+        for (int q = 0; q < KM; ++q)
+            if (q < k && (q % L) == lane) y[q] = acc[q];
+    }
+}
+
+// GROUP / BINNED: slot g (= global thread / L) computes row rows[g] (or g).
+template <typename V, typename T, int L, int KM>
+__global__ __launch_bounds__(kBlock) void k_spmv_group(
+    int32_t count, const int32_t *__restrict__ rows, const int32_t *__restrict__ rp,
+    const int32_t *__restrict__ col, const V *__restrict__ val, int32_t k,
+    const T *__restrict__ X, int64_t ldx, T *__restrict__ Y, int64_t ldy) {
+    const int64_t slot = ((int64_t)blockIdx.x * kBlock + threadIdx.x) / L;
+    const int lane = threadIdx.x % L;
+    if (slot >= count) return;                  // whole groups leave together
+    const int32_t row = rows ? rows[slot] : (int32_t)slot;
+    const int32_t s = ld_stream(rp + row), e = ld_stream(rp + row + 1);
+    T acc[KM];
+    row_dot<V, T, L, KM>(s, e, lane, col, val, k, X, ldx, acc);
+    store_row<T, L, KM>(Y, ldy, row, lane, k, acc);
+}
+
+// ---- merge path -------------------------------------------------------------------
+
+constexpr int kMergeIpt = 4;                          // path items per thread
+constexpr int kMergeTile = kBlock * kMergeIpt;        // path items per workgroup
+
+struct Coord { int32_t x, y; };                       // rows consumed, nonzeros consumed
+
+// Largest x in [max(0, d - nnz), min(d, M)] whose row ends precede the
+// nonzero at d - x: the merge of row_end[] = rp[1..M] with 0 .. nnz-1, where a
+// row end sorts before a nonzero of equal index.
+__device__ inline Coord merge_search(int64_t d, const int32_t *row_end, int32_t nrows,
+                                     int64_t nnz) {
+    int64_t lo = d - nnz > 0 ? d - nnz : 0;
+    int64_t hi = d < nrows ? d : nrows;
+    while (lo < hi) {
+        int64_t mid = (lo + hi) >> 1;
+        if ((int64_t)row_end[mid] <= d - mid - 1) lo = mid + 1;
+        else hi = mid;
+    }
+    return Coord{(int32_t)lo, (int32_t)(d - lo)};
+}
+
+__global__ __launch_bounds__(kBlock) void k_merge_coords(int32_t nrows, int64_t nnz,
+                                                         const int32_t *__restrict__ rp,
+                                                         int32_t ntiles, Coord *coords) {
+    int64_t w = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (w > ntiles) return;
+    int64_t total = (int64_t)nrows + nnz;
+    int64_t d = w * kMergeTile;
+    if (d > total) d = total;
+    coords[w] = merge_search(d, rp + 1, nrows, nnz);
+}
+
+struct Carry { int32_t row; int32_t pad; double v[4]; };   // row -1: none
+
+// Each workgroup stages its slice's products and row ends in LDS with
+// coalesced loads, walks the merge path in per-thread runs of kMergeIpt items,
+// finishes rows spanning threads with a segmented scan in LDS, writes the rows
+// that end inside the slice, and leaves the unfinished last row as a carry.
+template <typename V, typename T, int KM>
+__global__ __launch_bounds__(kBlock) void k_spmv_merge(
+    int32_t nrows, int64_t nnz, const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
+    const V *__restrict__ val, int32_t k, const T *__restrict__ X, int64_t ldx,
+    T *__restrict__ Y, int64_t ldy, const Coord *__restrict__ coords, Carry *carry) {
+    __shared__ T prod[kMergeTile][KM];
+    __shared__ int32_t row_end[kMergeTile + 1];
+    __shared__ int32_t key[kBlock];
+    __shared__ T part[kBlock][KM];
+    const Coord c0 = coords[blockIdx.x], c1 = coords[blockIdx.x + 1];
+    const int32_t nrow_t = c1.x - c0.x, nnz_t = c1.y - c0.y;
+    for (int i = threadIdx.x; i < nnz_t; i += kBlock) {
+        const int32_t p = c0.y + i;
+        const T a = ValLoad<V, T>::get(val + p);
+        const T *xr = X + (int64_t)ld_stream(col + p) * ldx;
+#pragma unroll
+        for (int q = 0; q < KM; ++q) prod[i][q] = (KM == 1 || q < k) ? a * xr[q] : T(0);
+    }
+    for (int i = threadIdx.x; i < nrow_t; i += kBlock) row_end[i] = ld_stream(rp + c0.x + 1 + i);
+    __syncthreads();
+    // this thread's start on the slice's path
+    const int32_t d = min((int32_t)threadIdx.x * kMergeIpt, nrow_t + nnz_t);
+    int32_t lo = max(0, d - nnz_t), hi = min(d, nrow_t);
+    while (lo < hi) {
+        int32_t mid = (lo + hi) >> 1;
+        if (row_end[mid] - c0.y <= d - mid - 1) lo = mid + 1;
+        else hi = mid;
+    }
+    int32_t tx = lo, ty = d - lo;
+    T acc[KM];
+#pragma unroll
+    for (int q = 0; q < KM; ++q) acc[q] = T(0);
+    int32_t first_done = -1;                          // first row this thread completes
+    T first_val[KM];
+#pragma unroll
+    for (int q = 0; q < KM; ++q) first_val[q] = T(0);
+    for (int it = 0; it < kMergeIpt; ++it) {
+        if (tx < nrow_t && row_end[tx] - c0.y <= ty) {        // row end
+            if (first_done < 0) {
+                first_done = tx;
+#pragma unroll
+                for (int q = 0; q < KM; ++q) first_val[q] = acc[q];
+            } else {
+                T *y = Y + (int64_t)(c0.x + tx) * ldy;
+#pragma unroll
+                for (int q = 0; q < KM; ++q)
+                    if (KM == 1 || q < k) y[q] = acc[q];
+            }
+#pragma unroll
+            for (int q = 0; q < KM; ++q) acc[q] = T(0);
+            ++tx;
+        } else if (ty < nnz_t) {                               // nonzero
+#pragma unroll
+            for (int q = 0; q < KM; ++q) acc[q] += prod[ty][q];
+            ++ty;
+        }
+    }
+    // carry of this thread: the row it is inside at the end (tx), partial acc
+    key[threadIdx.x] = tx;
+#pragma unroll
+    for (int q = 0; q < KM; ++q) part[threadIdx.x][q] = acc[q];
+    __syncthreads();
+    // inclusive segmented scan of the carries over threads with equal key
+    for (int off = 1; off < kBlock; off <<= 1) {
+        T v[KM];
+        const bool take = threadIdx.x >= off && key[threadIdx.x - off] == key[threadIdx.x];
+#pragma unroll
+        for (int q = 0; q < KM; ++q) v[q] = take ? part[threadIdx.x - off][q] : T(0);
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < KM; ++q) part[threadIdx.x][q] += v[q];
+        __syncthreads();
+    }
+    // the first row this thread completes began in earlier threads iff their
+    // carry key equals it
+    if (first_done >= 0) {
+        if (threadIdx.x > 0 && key[threadIdx.x - 1] == first_done) {
+#pragma unroll
+            for (int q = 0; q < KM; ++q) first_val[q] = part[threadIdx.x - 1][q] + first_val[q];
+        }
+        T *y = Y + (int64_t)(c0.x + first_done) * ldy;
+#pragma unroll
+        for (int q = 0; q < KM; ++q)
+            if (KM == 1 || q < k) y[q] = first_val[q];
+    }
+    // slice carry: the last thread's scanned partial for the row still open at
+    // the slice end. Once every row end of the slice is consumed that row is
+    // local index nrow_t, i.e. the next slice's first row c1.x.
+    if (threadIdx.x == kBlock - 1) {
+        Carry cr;
+        const int32_t open_row = c0.x + key[kBlock - 1];
+        cr.row = open_row < nrows ? open_row : -1;
+        cr.pad = 0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) cr.v[q] = q < KM ? (double)part[kBlock - 1][q] : 0.0;
+        carry[blockIdx.x] = cr;
+    }
+}
+
+// Rows crossing slices: the slice where the row ends wrote its own part;
+// add the carries of the earlier slices, in slice order.
+template <typename T, int KM>
+__global__ __launch_bounds__(kBlock) void k_merge_fixup(int32_t ntiles, const Carry *carry,
+                                                        int32_t k, T *__restrict__ Y,
+                                                        int64_t ldy) {
+    int32_t w = blockIdx.x * kBlock + threadIdx.x;
+    if (w >= ntiles) return;
+    const int32_t row = carry[w].row;
+    if (row < 0) return;
+    if (w > 0 && carry[w - 1].row == row) return;        // not the first carry of this row
+    double s[KM];
+#pragma unroll
+    for (int q = 0; q < KM; ++q) s[q] = 0.0;
+    // carries are partial sums in T; add them in T in slice order
+    T t[KM];
+#pragma unroll
+    for (int q = 0; q < KM; ++q) t[q] = T(0);
+    for (int32_t u = w; u < ntiles && carry[u].row == row; ++u)
+#pragma unroll
+        for (int q = 0; q < KM; ++q) t[q] += (T)carry[u].v[q];
+    T *y = Y + (int64_t)row * ldy;
+#pragma unroll
+    for (int q = 0; q < KM; ++q)
+        if (KM == 1 || q < k) y[q] = t[q] + y[q];
+    (void)s;
+}
+
+// ---- batched persistent kernel -------------------------------------------------------
+
+template <typename V, typename T, int L, int KM>
+__device__ inline void batch_tile(const BatchDesc &d, int32_t r0, int32_t r1) {
+    const int lane = threadIdx.x % L;
+    for (int32_t row = r0 + threadIdx.x / L; row < r1; row += kBlock / L) {
+        const int32_t s = ld_stream(d.rp + row), e = ld_stream(d.rp + row + 1);
+        T acc[KM];
+        row_dot<V, T, L, KM>(s, e, lane, d.col, (const V *)d.val, d.k, (const T *)d.X, d.ldx,
+                             acc);
+        store_row<T, L, KM>((T *)d.Y, d.ldy, row, lane, d.k, acc);
+    }
+}
+
+template <typename V, typename T, int L>
+__device__ inline void batch_tile_k(const BatchDesc &d, int32_t r0, int32_t r1) {
+    if (d.k <= 1) batch_tile<V, T, L, 1>(d, r0, r1);
+    else if (d.k <= 2) batch_tile<V, T, L, 2>(d, r0, r1);
+    else if (d.k <= 4) batch_tile<V, T, L, 4>(d, r0, r1);
+    else if (d.k <= 8) batch_tile<V, T, L, 8>(d, r0, r1);
+    else batch_tile<V, T, L, 16>(d, r0, r1);
+}
+
+template <typename V, typename T>
+__device__ inline void batch_tile_l(const BatchDesc &d, int32_t r0, int32_t r1) {
+    switch (d.lanes) {
+    case 1: batch_tile_k<V, T, 1>(d, r0, r1); break;
+    case 2: batch_tile_k<V, T, 2>(d, r0, r1); break;
+    case 4: batch_tile_k<V, T, 4>(d, r0, r1); break;
+    case 8: batch_tile_k<V, T, 8>(d, r0, r1); break;
+    case 16: batch_tile_k<V, T, 16>(d, r0, r1); break;
+    case 32: batch_tile_k<V, T, 32>(d, r0, r1); break;
+    default: batch_tile_k<V, T, 64>(d, r0, r1); break;
+    }
+}
+
+// Persistent grid: each workgroup takes the next tile index from a device
+// counter until all tiles of all matrices are done; every workgroup reaches
+// the exit test, so the grid always drains.
+__global__ __launch_bounds__(kBlock) void k_spmv_batch(const BatchDesc *__restrict__ descs,
+                                                       int32_t count, int32_t total_tiles,
+                                                       int32_t *counter) {
+    __shared__ int32_t tile_s;
+    for (;;) {
+        if (threadIdx.x == 0) tile_s = atomicAdd(counter, 1);
+        __syncthreads();
+        const int32_t tile = tile_s;
+        __syncthreads();
+        if (tile >= total_tiles) break;
+        int32_t lo = 0, hi = count - 1;               // last desc with tile_begin <= tile
+        while (lo < hi) {
+            int32_t mid = (lo + hi + 1) >> 1;
+            if (descs[mid].tile_begin <= tile) lo = mid;
+            else hi = mid - 1;
+        }
+        const BatchDesc d = descs[lo];
+        const int32_t r0 = (tile - d.tile_begin) * d.rows_per_tile;
+        const int32_t r1 = min(d.nrows, r0 + d.rows_per_tile);
+        if (d.vtype == VAL_F64) batch_tile_l<double, double>(d, r0, r1);
+        else if (d.vtype == VAL_F32) batch_tile_l<float, float>(d, r0, r1);
+        else batch_tile_l<uint16_t, float>(d, r0, r1);
+    }
+}
+
+__global__ void k_batch_reset(int32_t *counter) { *counter = 0; }
+
+// ---- launch helpers ---------------------------------------------------------------------
+
+template <typename V, typename T, int L, int KM>
+void group_launch(const SpmvArgs &a, const int32_t *rows, int32_t count, hipStream_t s) {
+    const int64_t threads = (int64_t)count * L;
+    const int grid = (int)cdiv(threads, kBlock);
+    hipLaunchKernelGGL((k_spmv_group<V, T, L, KM>), dim3(grid), dim3(kBlock), 0, s, count, rows,
+                       a.rp, a.col, (const V *)a.val, a.k, (const T *)a.X, a.ldx, (T *)a.Y, a.ldy);
+}
+
+template <typename V, typename T, int KM>
+hipError_t group_by_lanes(const SpmvArgs &a, int lanes, const int32_t *rows, int32_t count,
+                          hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    switch (lanes) {
+    case 1: group_launch<V, T, 1, KM>(a, rows, count, s); break;
+    case 2: group_launch<V, T, 2, KM>(a, rows, count, s); break;
+    case 4: group_launch<V, T, 4, KM>(a, rows, count, s); break;
+    case 8: group_launch<V, T, 8, KM>(a, rows, count, s); break;
+    case 16: group_launch<V, T, 16, KM>(a, rows, count, s); break;
+    case 32: group_launch<V, T, 32, KM>(a, rows, count, s); break;
+    case 64: group_launch<V, T, 64, KM>(a, rows, count, s); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <typename V, typename T, int KM>
+hipError_t merge_launch(const SpmvArgs &a, hipStream_t s) {
+    const int64_t total = (int64_t)a.nrows + a.nnz;
+    const int32_t ntiles = (int32_t)std::max<int64_t>(1, cdiv(total, kMergeTile));
+    Coord *coords = (Coord *)a.merge_ws;
+    Carry *carry = (Carry *)((char *)a.merge_ws + ((sizeof(Coord) * (ntiles + 1) + 255) & ~255ull));
+    hipLaunchKernelGGL(k_merge_coords, dim3(cdiv(ntiles + 1, kBlock)), dim3(kBlock), 0, s, a.nrows,
+                       a.nnz, a.rp, ntiles, coords);
+    hipLaunchKernelGGL((k_spmv_merge<V, T, KM>), dim3(ntiles), dim3(kBlock), 0, s, a.nrows, a.nnz,
+                       a.rp, a.col, (const V *)a.val, a.k, (const T *)a.X, a.ldx, (T *)a.Y, a.ldy,
+                       (const Coord *)coords, carry);
+    hipLaunchKernelGGL((k_merge_fixup<T, KM>), dim3(cdiv(ntiles, kBlock)), dim3(kBlock), 0, s,
+                       ntiles, (const Carry *)carry, a.k, (T *)a.Y, a.ldy);
+    return hipGetLastError();
+}
+
+template <typename V, typename T, int KM>
+hipError_t spmv_k(const SpmvArgs &a, int variant, hipStream_t s) {
+    const int family = variant & 0xf00, lanes = variant & 0xff;
+    if (family == MXE_VAR_GROUP) return group_by_lanes<V, T, KM>(a, lanes, nullptr, a.nrows, s);
+    if (family == MXE_VAR_BINNED) {
+        for (int b = 0; b < kNumBins; ++b) {
+            const int32_t n = a.bin_off_host[b + 1] - a.bin_off_host[b];
+            hipError_t e = group_by_lanes<V, T, KM>(a, 1 << b, a.bin_list + a.bin_off_host[b], n, s);
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    }
+    if (family == MXE_VAR_MERGE) {
+        if constexpr (KM <= 4) return merge_launch<V, T, KM>(a, s);
+        return hipErrorInvalidValue;
+    }
+    return hipErrorInvalidValue;
+}
+
+template <typename V, typename T>
+hipError_t spmv_t(const SpmvArgs &a, int variant, hipStream_t s) {
+    if (a.k <= 1) return spmv_k<V, T, 1>(a, variant, s);
+    if (a.k <= 2) return spmv_k<V, T, 2>(a, variant, s);
+    if (a.k <= 4) return spmv_k<V, T, 4>(a, variant, s);
+    if (a.k <= 8) return spmv_k<V, T, 8>(a, variant, s);
+    if (a.k <= 16) return spmv_k<V, T, 16>(a, variant, s);
+    return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+size_t merge_ws_bytes(int32_t nrows, int64_t nnz) {
+    const int64_t ntiles = std::max<int64_t>(1, cdiv((int64_t)nrows + nnz, kMergeTile));
+    return ((sizeof(Coord) * (ntiles + 1) + 255) & ~255ull) + sizeof(Carry) * ntiles + 256;
+}
+
+hipError_t launch_spmv(const SpmvArgs &a, int variant, hipStream_t s) {
+    if (a.nrows <= 0) return hipSuccess;
+    if ((variant & 0xf00) == MXE_VAR_SLAB) {
+        if (!a.slab) return hipErrorInvalidValue;
+        return launch_spmv_slab(*a.slab, a.vtype, a.slab_off, a.slab_idx, a.slab_val, a.k, a.X,
+                                a.ldx, a.Y, a.ldy, s);
+    }
+    switch (a.vtype) {
+    case VAL_F64: return spmv_t<double, double>(a, variant, s);
+    case VAL_F32: return spmv_t<float, float>(a, variant, s);
+    case VAL_BF16: return spmv_t<uint16_t, float>(a, variant, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_batch_reset(int32_t *counter, hipStream_t s) {
+    hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(1), 0, s, counter);
+    return hipGetLastError();
+}
+
+int32_t batch_grid_size() { return 256 * 8; }   // 8 resident workgroups per CU
+
+hipError_t launch_spmv_batch(const BatchDesc *descs, int32_t count, int32_t total_tiles,
+                             int32_t *counter, int32_t grid, hipStream_t s) {
+    if (count <= 0 || total_tiles <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_spmv_batch, dim3(grid), dim3(kBlock), 0, s, descs, count, total_tiles,
+                       counter);
+    return hipGetLastError();
+}
+
+}  // namespace mxe

@@ -1,0 +1,122 @@
+// Host-side runtime state behind the C ABI (context, matrices, plans,
+// serving loop). Shared by api.cpp and serve.cpp.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "../../include/mxe.h"
+#include "internal.h"
+
+namespace mxe {
+
+void set_error(const std::string &msg);
+mxe_status fail(mxe_status s, const std::string &msg);
+mxe_status hip_fail(hipError_t e, const char *what);
+
+#define MXE_HIP(call)                                                   \
+    do {                                                                \
+        hipError_t _e = (call);                                         \
+        if (_e != hipSuccess) return ::mxe::hip_fail(_e, #call);        \
+    } while (0)
+
+struct Matrix {
+    int64_t id = 0;
+    int32_t nrows = 0, ncols = 0;
+    int64_t nnz = 0;
+    mxe_dtype storage = MXE_F64;
+    int32_t *rp = nullptr, *col = nullptr;
+    void *val = nullptr;
+    // permutation (device, new-to-old and old-to-new); null when not permuted
+    int32_t *rperm = nullptr, *cperm = nullptr, *rinv = nullptr, *cinv = nullptr;
+    std::shared_ptr<Matrix> parent;
+    uint64_t seed = 0;
+    uint32_t mode = 0;
+    uint64_t bytes = 0;                 // HBM held
+    // lazily built
+    int32_t max_row = -1;
+    int32_t *bin_list = nullptr;
+    int32_t *bin_off_dev = nullptr;
+    int32_t bin_off[kNumBins + 1] = {};
+    bool bins_ready = false;
+    void *merge_ws = nullptr;
+    struct Slab {
+        SlabGeom g;
+        int32_t *off = nullptr;
+        uint32_t *idx = nullptr;
+        void *val = nullptr;
+    };
+    std::map<std::pair<int, int>, Slab> slabs;   // (k class, slab size in 64 KiB) -> layout
+    std::atomic<int> busy{0};           // serving requests queued or running
+    std::vector<void *> allocs;         // device allocations to free
+};
+
+struct TuneKey {
+    int32_t nrows, ncols;
+    int64_t nnz;
+    int32_t storage, kclass;
+    uint64_t seed;
+    uint32_t mode;
+    int64_t root;                       // id of the unpermuted ancestor
+    bool operator<(const TuneKey &o) const {
+        return std::tie(nrows, ncols, nnz, storage, kclass, seed, mode, root) <
+               std::tie(o.nrows, o.ncols, o.nnz, o.storage, o.kclass, o.seed, o.mode, o.root);
+    }
+};
+struct TuneResult { int variant; int group_lanes; };
+
+struct Plan {
+    std::vector<mxe_item> items;
+    std::vector<BatchDesc> descs;
+    BatchDesc *descs_dev = nullptr;
+    int32_t *counter = nullptr;
+    int32_t total_tiles = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipStream_t capture_stream = nullptr;
+};
+
+struct Server;
+
+}  // namespace mxe
+
+struct mxe_ctx {
+    int device = 0;
+    uint64_t budget = 0;                // 0: no cap
+    std::atomic<uint64_t> used{0};      // resident bytes
+    std::recursive_mutex mu;            // serializes non-serving calls
+    std::map<int64_t, std::shared_ptr<mxe::Matrix>> mats;
+    std::map<mxe::TuneKey, mxe::TuneResult> tuned;
+    std::map<int64_t, std::unique_ptr<mxe::Plan>> plans;
+    int64_t next_id = 1;
+    int cu_count = 256;
+    mxe::Server *server = nullptr;      // owned; created and deleted by the serving loop
+};
+
+namespace mxe {
+
+// internal helpers implemented in api.cpp, used by serve.cpp
+std::shared_ptr<Matrix> find_matrix(mxe_ctx *ctx, mxe_mat m);
+mxe_status spmv_internal(mxe_ctx *ctx, Matrix &A, int32_t k, const void *X, int64_t ldx, void *Y,
+                         int64_t ldy, uint32_t flags, hipStream_t s);
+mxe_status ensure_variant(mxe_ctx *ctx, Matrix &A, int32_t k, hipStream_t s, TuneResult *out);
+int elem_bytes_of(mxe_dtype d);
+uint64_t request_bytes(const Matrix &A, int32_t k);
+
+// serving loop (serve.cpp)
+mxe_status serve_start(mxe_ctx *ctx, const mxe_serve_config *cfg);
+mxe_status serve_submit(mxe_ctx *ctx, const mxe_item *req, mxe_ticket *out);
+mxe_status serve_wait(mxe_ctx *ctx, mxe_ticket t, int64_t timeout_us, double *latency_us);
+mxe_status serve_stop(mxe_ctx *ctx);
+void serve_destroy(mxe_ctx *ctx);
+
+}  // namespace mxe

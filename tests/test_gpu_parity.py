@@ -1,0 +1,299 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Integer results (permutations, permuted CSR, histograms) and the correctly
+rounded entropy must match bit for bit; products must stay within
+max_i |y - y_ref| / (|A||x|)_i of 1e-13 (FP64), 1e-5 (FP32 values) and 1e-2
+(BF16 values, FP32 accumulation) against the FP64 oracle."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_common import TOL, expected_export, spmv_error, torch_vec
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+mx = pytest.importorskip("paper_2308_00106_amd.mxe")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = mx.Context(0)
+    yield c
+    c.close()
+
+
+def _diag(n, m=None):
+    m = n if m is None else m
+    k = min(n, m)
+    rp = np.concatenate([np.arange(k + 1), np.full(n - k, k)]).astype(np.int32)
+    return synth.CSR(n, m, rp, np.arange(k, dtype=np.int32), np.ones(k))
+
+
+# --- permutations -------------------------------------------------------------
+
+@pytest.mark.parametrize("n", [1, 2, 7, 48, 49, 50, 1000, 4096, 100_003, 2_000_000])
+def test_permutation_matches_oracle(ctx, n):
+    m = max(1, n // 3 + 5)
+    A = ctx.register(_diag(n, m))
+    for seed in (3, 0, 2**64 - 1):
+        B = ctx.permute(A, seed)
+        rp, cp = ctx.get_permutation(B)
+        s_r, s_c = oracle.stream_seeds(seed)
+        assert np.array_equal(rp, oracle.permutation(n, s_r)), (n, seed)
+        assert np.array_equal(cp, oracle.permutation(m, s_c)), (n, seed)
+        ctx.release(B)
+    ctx.release(A)
+
+
+def test_permute_modes_identity_parts(ctx):
+    A0 = synth.random_csr(300, 200, 0.05, 1)
+    A = ctx.register(A0)
+    B = ctx.permute(A, 9, mx.ROWS)
+    rp, cp = ctx.get_permutation(B)
+    assert np.array_equal(cp, np.arange(200))
+    assert np.array_equal(rp, oracle.permute(A0, 9, oracle.ROWS)[0])
+    C = ctx.permute(A, 9, mx.COLS)
+    rp, cp = ctx.get_permutation(C)
+    assert np.array_equal(rp, np.arange(300))
+    assert np.array_equal(cp, oracle.permute(A0, 9, oracle.COLS)[1])
+    for H in (B, C, A):
+        ctx.release(H)
+
+
+# --- permuted CSR ---------------------------------------------------------------
+
+CSR_CASES = [
+    ("config1", lambda: synth.config1(1)),
+    ("ragged", lambda: synth.random_csr(4096 * 3 + 17, 9001, 0.002, 2, empty_rows=0.1)),
+    ("wide", lambda: synth.random_csr(333, 20000, 0.01, 3)),
+    ("long_rows", lambda: synth.random_csr(700, 3000, 0.15, 4)),     # rows > 256: global path
+    ("empty", lambda: synth.random_csr(50, 60, 0.0, 5)),
+    ("skewed", lambda: synth.config3(1, n=60_000)),
+]
+
+
+@pytest.mark.parametrize("name,make", CSR_CASES)
+@pytest.mark.parametrize("storage", ["f64", "f32", "bf16"])
+def test_permuted_csr_bit_exact(ctx, name, make, storage):
+    A0 = make()
+    A = ctx.register(A0, storage)
+    for mode in (mx.ROWS | mx.COLS, mx.ROWS, mx.COLS):
+        B = ctx.permute(A, 3, mode)
+        rperm, cperm = ctx.get_permutation(B)
+        er, ec, ev = expected_export(A0, rperm, cperm, storage)
+        gr, gc, gv = ctx.export_csr(B)
+        assert np.array_equal(gr, er), (name, mode)
+        assert np.array_equal(gc, ec), (name, mode)
+        assert np.array_equal(gv.view(np.uint8), np.asarray(ev).view(np.uint8)), (name, mode)
+        ctx.release(B)
+    ctx.release(A)
+
+
+def test_registered_values_round_once(ctx):
+    """BF16/FP32 storage equals one round-to-nearest-even from FP64."""
+    vals = np.array([1 + 2**-8 + 2**-30, 1 + 2**-8, 1 + 3 * 2**-8, -(2 - 2**-8) * 2.0**127,
+                     1.5 * 2.0**-133, 2.0**-126 - 2.0**-134, 0.1, -0.0, 3.0e38, 1e-45])
+    n = len(vals)
+    A0 = synth.CSR(1, n, np.array([0, n], np.int32), np.arange(n, dtype=np.int32), vals)
+    for storage, ref in (("bf16", oracle.round_bf16(vals)), ("f32", oracle.round_f32(vals))):
+        A = ctx.register(A0, storage)
+        _, _, gv = ctx.export_csr(A)
+        assert np.array_equal(gv.view(np.uint8), ref.view(np.uint8)), storage
+        ctx.release(A)
+
+
+# --- histogram and entropy -----------------------------------------------------
+
+@pytest.mark.parametrize("case,grid", [("config1", (64, 64)), ("config1", (1, 1)),
+                                       ("config1", (7, 3)), ("config1", (4096, 1)),
+                                       ("ragged", (64, 64)), ("wide", (5, 1000)),
+                                       ("skewed", (1024, 1024)), ("skewed", (3, 20000))])
+def test_histogram_and_entropy_exact(ctx, case, grid):
+    A0 = dict(CSR_CASES)[case]()
+    A = ctx.register(A0)
+    B = ctx.permute(A, 3)
+    for H in (A, B):
+        rp, col, _ = ctx.export_csr(H)
+        bits, nats, hist = ctx.entropy(H, grid[0], grid[1], hist=True)
+        ref = oracle.block_hist(A0.nrows, A0.ncols, rp, col, grid[0], grid[1])
+        assert np.array_equal(hist, ref), case
+        assert (bits, nats) == oracle.entropy(ref), case
+    ctx.release(B)
+    ctx.release(A)
+
+
+def test_entropy_uniform_fill_and_single_block(ctx):
+    U = ctx.register(synth.uniform_fill(4096, 64, 16))
+    assert ctx.entropy(U, 64, 64)[0] == 12.0
+    assert ctx.entropy(U, 1, 1) == (0.0, 0.0)
+    ctx.release(U)
+    E = ctx.register(synth.random_csr(10, 10, 0.0, 1))
+    assert ctx.entropy(E, 4, 4) == (0.0, 0.0)
+    ctx.release(E)
+
+
+def test_entropy_permuted_config1(ctx):
+    A0 = synth.config1(1)
+    A = ctx.register(A0)
+    B = ctx.permute(A, 3)
+    h0, h1 = ctx.entropy(A, 64, 64)[0], ctx.entropy(B, 64, 64)[0]
+    assert h0 < h1 <= 12.0
+    ctx.release(B)
+    ctx.release(A)
+
+
+def test_entropy_rejects_bad_grid(ctx):
+    A = ctx.register(synth.config1(1))
+    for g in ((0, 4), (4, 0), (2**20 + 1, 1)):
+        with pytest.raises(mx.MxeError) as e:
+            ctx.entropy(A, *g)
+        assert e.value.status == mx.ERR_INVALID_ARG
+    ctx.release(A)
+
+
+# --- products -------------------------------------------------------------------
+
+VARIANTS = [mx.variant(mx.VAR_GROUP, lanes) for lanes in (1, 2, 4, 8, 16, 32, 64)] + \
+           [mx.variant(mx.VAR_BINNED), mx.variant(mx.VAR_MERGE),
+            mx.variant(mx.VAR_SLAB, 1), mx.variant(mx.VAR_SLAB, 32)]   # 64 KiB and 2 MiB slabs
+
+
+def _force(ctx, H, k, v):
+    """Forces variant v for every column chunk of a k-column product; False
+    when the library declines it for this matrix (e.g. too many slabs)."""
+    try:
+        ctx.set_variant(H, min(k, 16), v)
+        if k > 16:
+            ctx.set_variant(H, k - 16, v)
+    except mx.MxeError as e:
+        if e.status == mx.ERR_UNSUPPORTED:
+            return False
+        raise
+    return True
+
+
+@pytest.mark.parametrize("name,make", CSR_CASES)
+@pytest.mark.parametrize("k", [1, 2, 3, 16, 17])
+def test_spmv_all_variants_f64(ctx, name, make, k):
+    A0 = make()
+    X = synth.vector(A0.ncols, 2, k=k)
+    A = ctx.register(A0)
+    B = ctx.permute(A, 3)
+    rperm, cperm = ctx.get_permutation(B)
+    Bo = synth.CSR(A0.nrows, A0.ncols, *oracle.permute_csr(A0, rperm, cperm))
+    for H, Ho in ((A, A0), (B, Bo)):
+        Xt = torch_vec(X, torch.float64)
+        for v in VARIANTS:
+            if not _force(ctx, H, k, v):
+                continue
+            Y = torch.full((A0.nrows, k) if k > 1 else (A0.nrows,), float("nan"),
+                           dtype=torch.float64, device="cuda")
+            ctx.spmv(H, Xt, Y)
+            torch.cuda.synchronize()
+            err = spmv_error(Ho, X, Y.cpu().numpy(), "f64")
+            assert err <= TOL["f64"], (name, k, hex(v), err)
+    ctx.release(B)
+    ctx.release(A)
+
+
+@pytest.mark.parametrize("storage", ["f32", "bf16"])
+@pytest.mark.parametrize("name,make", CSR_CASES[:4] + CSR_CASES[5:])
+def test_spmv_reduced_precision(ctx, storage, name, make):
+    A0 = make()
+    for k in (1, 4, 8):
+        X = synth.vector(A0.ncols, 2, k=k)
+        A = ctx.register(A0, storage)
+        Xt = torch_vec(X, torch.float32)
+        for v in VARIANTS:
+            if not _force(ctx, A, k, v):
+                continue
+            Y = torch.full((A0.nrows, k) if k > 1 else (A0.nrows,), float("nan"),
+                           dtype=torch.float32, device="cuda")
+            ctx.spmv(A, Xt, Y)
+            torch.cuda.synchronize()
+            Yh = Y.cpu().numpy().astype(np.float64)
+            err = spmv_error(A0, X, Yh, storage)           # vs FP64 oracle, original values
+            assert err <= TOL[storage], (name, storage, k, hex(v), err)
+        ctx.release(A)
+
+
+def test_identity_original_space(ctx):
+    """y = P_r^-1 ((P_r A P_c)(P_c^-1 x)) equals A x (Eq. 1), via the
+    original-space flag and via explicit gather / scatter."""
+    A0 = synth.config1(1)
+    x = synth.vector(A0.ncols, 2)
+    A = ctx.register(A0)
+    B = ctx.permute(A, 3)
+    xt = torch_vec(x, torch.float64)
+    y = torch.empty(A0.nrows, dtype=torch.float64, device="cuda")
+    ctx.spmv(B, xt, y, flags=mx.SPACE_ORIGINAL)
+    torch.cuda.synchronize()
+    assert spmv_error(A0, x, y.cpu().numpy(), "f64") <= 1e-13
+    xp = torch.empty_like(xt)
+    yp = torch.empty_like(y)
+    y2 = torch.empty_like(y)
+    ctx.gather_x(B, xt, xp)
+    ctx.spmv(B, xp, yp)
+    ctx.scatter_y(B, yp, y2)
+    torch.cuda.synchronize()
+    _, cperm = ctx.get_permutation(B)
+    assert np.array_equal(xp.cpu().numpy(), x[cperm])
+    assert spmv_error(A0, x, y2.cpu().numpy(), "f64") <= 1e-13
+    ctx.release(B)
+    ctx.release(A)
+
+
+def test_runs_are_bitwise_deterministic(ctx):
+    A0 = synth.config3(1, n=40_000)
+    A = ctx.register(A0)
+    x = torch_vec(synth.vector(A0.ncols, 2), torch.float64)
+    outs = []
+    for _ in range(2):
+        B = ctx.permute(A, 11)
+        y = torch.empty(A0.nrows, dtype=torch.float64, device="cuda")
+        ctx.spmv(B, x, y)
+        torch.cuda.synchronize()
+        outs.append((ctx.export_csr(B), y.cpu().numpy(), ctx.entropy(B, 256, 256)))
+        ctx.release(B)
+    (c1, y1, h1), (c2, y2, h2) = outs
+    for a, b in zip(c1, c2):
+        assert np.array_equal(a, b)
+    assert np.array_equal(y1.view(np.uint64), y2.view(np.uint64))
+    assert h1 == h2
+    ctx.release(A)
+
+
+# --- full-size configuration, as the benchmark runs it ------------------------------
+
+def test_full_size_config2(ctx):
+    """n = 2,000,000 block-clustered matrix: permutation, permuted CSR,
+    1024 x 1024 entropy and the tuned SpMV against the oracle in full."""
+    A0 = synth.config2(1)
+    x = synth.vector(A0.ncols, 2)
+    A = ctx.register(A0)
+    B = ctx.permute(A, 3)
+    rperm, cperm = ctx.get_permutation(B)
+    s_r, s_c = oracle.stream_seeds(3)
+    assert np.array_equal(rperm, oracle.permutation(A0.nrows, s_r))
+    assert np.array_equal(cperm, oracle.permutation(A0.ncols, s_c))
+    er, ec, ev = expected_export(A0, rperm, cperm, "f64")
+    gr, gc, gv = ctx.export_csr(B)
+    assert np.array_equal(gr, er) and np.array_equal(gc, ec) and np.array_equal(gv, ev)
+    bits, nats, hist = ctx.entropy(B, 1024, 1024, hist=True)
+    ref = oracle.block_hist(A0.nrows, A0.ncols, er, ec, 1024, 1024)
+    assert np.array_equal(hist, ref)
+    assert (bits, nats) == oracle.entropy(ref)
+    Bo = synth.CSR(A0.nrows, A0.ncols, er, ec, ev)
+    xt = torch_vec(x, torch.float64)
+    for H, Ho in ((A, A0), (B, Bo)):
+        ctx.tune(H, 1)
+        y = torch.empty(A0.nrows, dtype=torch.float64, device="cuda")
+        ctx.spmv(H, xt, y)
+        torch.cuda.synchronize()
+        assert spmv_error(Ho, x, y.cpu().numpy(), "f64") <= 1e-13
+    ctx.release(B)
+    ctx.release(A)
