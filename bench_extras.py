@@ -1,0 +1,220 @@
+"""Extra measurements for bench.py --extras (one GPU):
+
+  skewed      4,000,000-row CSR, lognormal row lengths capped at 256, columns
+              Gaussian around the diagonal; values stored FP64 / FP32 / BF16
+              (FP32 accumulation for the reduced ones): permuted vs original
+              SpMV and the error against the FP64 oracle on the FP64 values.
+  batch       64 matrices (rows log-uniform in [10k, 500k], 8-32 nnz per row,
+              block-clustered), k in {1, 2, 4, 8, 16}, FP32; one persistent
+              launch replayed from a HIP graph.
+  serving     32 resident permuted matrices of 50k-2M rows (FP32), requests of
+              1-8 right-hand sides on a random matrix; closed-loop saturation
+              rate, then open-loop Poisson arrivals at 0.5 and 0.8 of it:
+              p50 / p99 latency and aggregate GB/s.
+"""
+from __future__ import annotations
+
+import threading
+import time
+
+import numpy as np
+
+import oracle
+import synth
+
+
+def _bytes(A, val_bytes, vec_bytes, k):
+    return A.nnz * (val_bytes + 4) + (A.nrows + 1) * 4 + k * (A.ncols + A.nrows) * vec_bytes
+
+
+def _time(ctx, m, X, Y, reps, stream, flags=0):
+    import torch
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ctx.spmv(m, X, Y, flags=flags, stream=stream)
+    e0.record(stream)
+    for _ in range(reps):
+        ctx.spmv(m, X, Y, flags=flags, stream=stream)
+    e1.record(stream)
+    e1.synchronize()
+    return e0.elapsed_time(e1) * 1e3 / reps
+
+
+def skewed(ctx, log, n=4_000_000, reps=50):
+    import torch
+    from paper_2308_00106_amd import mxe as mx
+    stream = torch.cuda.current_stream()
+    t = time.perf_counter()
+    A0 = synth.config3(1, n=n)
+    x = synth.vector(A0.ncols, 2)
+    log(f"skewed: generated n={n} nnz={A0.nnz} in {time.perf_counter() - t:.1f}s")
+    yref = oracle.spmv(A0, x)
+    out = {"n": n, "nnz": A0.nnz, "max_row": int(A0.row_lengths().max())}
+    for st in ("f64", "f32", "bf16"):
+        A = ctx.register(A0, st)
+        B = ctx.permute(A, 3, stream=stream)
+        tdt = torch.float64 if st == "f64" else torch.float32
+        xt = torch.from_numpy(x).to(device="cuda", dtype=tdt)
+        y = torch.empty(A0.nrows, dtype=tdt, device="cuda")
+        r = {}
+        for name, H in (("permuted", B), ("original", A)):
+            v = ctx.tune(H, 1, stream=stream)
+            us = _time(ctx, H, xt, y, reps, stream)
+            vb = {"f64": 8, "f32": 4, "bf16": 2}[st]
+            nb = _bytes(A0, vb, 8 if st == "f64" else 4, 1)
+            r[name] = {"us": round(us, 2), "gbs": round(nb / (us * 1e-6) / 1e9, 1), "variant": hex(v)}
+        r["permuted_over_original"] = round(r["original"]["us"] / r["permuted"]["us"], 4)
+        ctx.spmv(B, xt, y, flags=mx.SPACE_ORIGINAL, stream=stream)
+        torch.cuda.synchronize()
+        r["max_normalized_error_vs_fp64_oracle"] = oracle.normalized_error(
+            A0.nrows, A0.row_ptr, A0.col, A0.val, x, y.cpu().numpy().astype(np.float64), yref)
+        r["entropy_bits_1024"] = {"original": ctx.entropy(A, 1024, 1024)[0],
+                                  "permuted": ctx.entropy(B, 1024, 1024)[0]}
+        out[st] = r
+        log(f"skewed {st}: {r}")
+        ctx.release(B)
+        ctx.release(A)
+    return out
+
+
+def batch(ctx, log, count=64, replays=20):
+    import torch
+    stream = torch.cuda.current_stream()
+    t = time.perf_counter()
+    mats, ks = [], []
+    for i in range(count):
+        A, k = synth.config4(i)
+        mats.append(A)
+        ks.append(k)
+    log(f"batch: generated {count} matrices, {sum(A.nnz for A in mats)} nnz in "
+        f"{time.perf_counter() - t:.1f}s")
+    hs = [ctx.permute(ctx.register(A, "f32"), 1000 + i, stream=stream) for i, A in enumerate(mats)]
+    Xs = [torch.rand((A.ncols, k), dtype=torch.float32, device="cuda") * 2 - 1 for A, k in zip(mats, ks)]
+    Ys = [torch.empty((A.nrows, k), dtype=torch.float32, device="cuda") for A, k in zip(mats, ks)]
+    items = list(zip(hs, Xs, Ys))
+    plan = ctx.batch_create(items)
+    ctx.batch_launch(plan, stream=stream)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(replays):
+        ctx.batch_launch(plan, stream=stream)
+    e1.record(stream)
+    e1.synchronize()
+    us = e0.elapsed_time(e1) * 1e3 / replays
+    nb = sum(_bytes(A, 4, 4, k) for A, k in zip(mats, ks))
+    flops = sum(2 * A.nnz * k for A, k in zip(mats, ks))
+    # error of one member against the FP64 oracle (permuted space)
+    j = int(np.argmax([A.nrows for A in mats]))
+    rperm, cperm = ctx.get_permutation(hs[j])
+    Bo = synth.CSR(mats[j].nrows, mats[j].ncols, *oracle.permute_csr(mats[j], rperm, cperm))
+    X = Xs[j].double().cpu().numpy()
+    err = oracle.normalized_error(Bo.nrows, Bo.row_ptr, Bo.col, Bo.val, X,
+                                  Ys[j].double().cpu().numpy(),
+                                  oracle.spmm(Bo.nrows, Bo.row_ptr, Bo.col, Bo.val, X))
+    ctx.batch_destroy(plan)
+    for h in hs:
+        ctx.release(h)
+    out = {"matrices": count, "rows": sum(A.nrows for A in mats), "nnz": sum(A.nnz for A in mats),
+           "k_mix": {str(k): ks.count(k) for k in sorted(set(ks))}, "us_per_batch": round(us, 1),
+           "gbs": round(nb / (us * 1e-6) / 1e9, 1), "gflops": round(flops / (us * 1e-6) / 1e9, 1),
+           "bytes_per_batch": nb, "max_normalized_error_sample": err,
+           "launch": "one persistent kernel per batch, replayed from a HIP graph"}
+    log(f"batch: {out}")
+    return out
+
+
+def serving(ctx_unused, log, pool=32, warm=1000, n_req=20000):
+    import torch
+    from paper_2308_00106_amd import mxe as mx
+    t = time.perf_counter()
+    mats = [synth.config5(i) for i in range(pool)]
+    log(f"serving: generated {pool} matrices, {sum(A.nrows for A in mats)} rows, "
+        f"{sum(A.nnz for A in mats)} nnz in {time.perf_counter() - t:.1f}s")
+    budget = 200 * (1 << 30)
+    with mx.Context(0, budget_bytes=budget) as ctx:
+        hs = [ctx.permute(ctx.register(A, "f32"), 1000 + i) for i, A in enumerate(mats)]
+        Xs = [torch.rand((A.ncols, 8), dtype=torch.float32, device="cuda") * 2 - 1 for A in mats]
+        slots = 32
+        Ys = [[torch.empty((A.nrows, 8), dtype=torch.float32, device="cuda") for _ in range(slots)]
+              for A in mats]
+        for h in hs:                        # tune every k class up front
+            for k in (1, 2, 4, 8, 16):
+                ctx.tune(h, k)
+        rng = np.random.default_rng(5)
+        total = warm + n_req
+        mi = rng.integers(0, pool, size=total)
+        ki = rng.integers(1, 9, size=total)
+        nbytes = np.array([_bytes(mats[m], 4, 4, k) for m, k in zip(mi, ki)], dtype=np.float64)
+        ctx.serve_start(streams=4, max_inflight=32, max_merge_k=16)
+
+        def run(rate, window=256):
+            """rate None: closed loop (as fast as possible, at most `window`
+            requests outstanding); else open-loop Poisson arrivals."""
+            tickets = [0] * total
+            finished = np.zeros(total, dtype=bool)
+            lat = np.zeros(total)
+            slot_use = [0] * pool
+            slot_owner = [[-1] * slots for _ in range(pool)]
+            done = threading.Event()
+
+            def waiter():
+                for i in range(total):
+                    while tickets[i] == 0:
+                        time.sleep(0)
+                    lat[i] = ctx.wait(tickets[i])
+                    finished[i] = True
+                done.set()
+
+            wt = threading.Thread(target=waiter)
+            wt.start()
+            gaps = rng.exponential(1.0 / rate, size=total) if rate else None
+            t_next = time.perf_counter()
+            t_meas = None
+            n_done = 0
+            for i in range(total):
+                if i == warm:
+                    t_meas = time.perf_counter()
+                if rate:
+                    t_next += gaps[i]
+                    while time.perf_counter() < t_next:
+                        pass
+                else:
+                    while i - n_done >= window:
+                        while n_done < i and finished[n_done]:
+                            n_done += 1
+                        time.sleep(0)
+                m, k = int(mi[i]), int(ki[i])
+                s = slot_use[m] % slots
+                slot_use[m] += 1
+                owner = slot_owner[m][s]
+                while owner >= 0 and not finished[owner]:   # the slot's last writer is done
+                    time.sleep(0)
+                slot_owner[m][s] = i
+                tickets[i] = ctx.submit(hs[m], Xs[m][:, :k], Ys[m][s][:, :k])
+            done.wait()
+            t1 = time.perf_counter()
+            wt.join()
+            meas = lat[warm:]
+            return {"requests": n_req, "seconds": round(t1 - t_meas, 4),
+                    "req_per_s": round(n_req / (t1 - t_meas), 1),
+                    "gbs": round(nbytes[warm:].sum() / (t1 - t_meas) / 1e9, 1),
+                    "p50_us": round(float(np.percentile(meas, 50)), 1),
+                    "p99_us": round(float(np.percentile(meas, 99)), 1),
+                    "mean_us": round(float(meas.mean()), 1)}
+
+        closed = run(None)
+        log(f"serving closed loop: {closed}")
+        rmax = closed["req_per_s"]
+        out = {"pool": pool, "rows": sum(A.nrows for A in mats), "nnz": sum(A.nnz for A in mats),
+               "budget_bytes": budget, "closed_loop": closed}
+        for frac in (0.5, 0.8):
+            r = run(frac * rmax)
+            r["offered_req_per_s"] = round(frac * rmax, 1)
+            out[f"poisson_{frac}"] = r
+            log(f"serving poisson {frac}: {r}")
+        ctx.serve_stop()
+    return out
+
+
+def run_all(ctx, log):
+    return {"skewed": skewed(ctx, log), "batch": batch(ctx, log), "serving": serving(ctx, log)}

@@ -278,7 +278,8 @@ static mxe_status tune(mxe_ctx *ctx, Matrix &A, int32_t k, hipStream_t s, TuneRe
     for (int v : cands) {
         SpmvArgs a;
         if ((result = prepare_args(ctx, A, v, kc, xs.p, kc, ys.p, kc, s, &a))) {
-            if (result == MXE_ERR_UNSUPPORTED) {
+            // a layout that does not fit the matrix or the HBM budget is not a candidate
+            if (result == MXE_ERR_UNSUPPORTED || result == MXE_ERR_BUDGET) {
                 result = MXE_OK;
                 continue;
             }

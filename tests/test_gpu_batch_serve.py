@@ -1,0 +1,207 @@
+"""GPU: uneven multi-matrix batches in one persistent launch (plain and
+replayed from a HIP graph), and the continuous-batching serving loop. Each
+result is checked against the FP64 oracle and against the same product run
+alone."""
+import threading
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_common import TOL, spmv_error, torch_vec
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+mx = pytest.importorskip("paper_2308_00106_amd.mxe")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = mx.Context(0)
+    yield c
+    c.close()
+
+
+def _pool(n_mats, seed, rows=(10_000, 60_000)):
+    """Small stand-ins for the batch and serving pools: log-uniform sizes,
+    block-clustered (8-32 per row) and skewed clustered structures."""
+    rng = np.random.default_rng(seed)
+    mats = []
+    for i in range(n_mats):
+        n = int(np.exp(rng.uniform(np.log(rows[0]), np.log(rows[1]))))
+        if i % 2 == 0:
+            mats.append(synth.block_clustered(n, rng.integers(8, 33, size=n), 4096, 0.9, seed + i))
+        else:
+            mats.append(synth.skewed_clustered(n, 2.0, 1.0, 256, 2000.0, seed + i))
+    return mats
+
+
+def _rand_x(A, k, seed):
+    return synth.vector(A.ncols, seed, k=k) if k > 1 else synth.vector(A.ncols, seed)
+
+
+def _empty_y(A, k):
+    return torch.full((A.nrows, k) if k > 1 else (A.nrows,), float("nan"), dtype=torch.float32,
+                      device="cuda")
+
+
+# --- batches ---------------------------------------------------------------------
+
+def test_batch_uneven_multi_rhs(ctx):
+    mats = _pool(8, 100)
+    ks = [1, 2, 4, 8, 16, 3, 5, 16]
+    handles = [ctx.permute(ctx.register(A, "f32"), 7) for A in mats]
+    B0 = []
+    for H, A in zip(handles, mats):
+        rperm, cperm = ctx.get_permutation(H)
+        B0.append(synth.CSR(A.nrows, A.ncols, *oracle.permute_csr(A, rperm, cperm)))
+    Xs = [_rand_x(A, k, 10 + i) for i, (A, k) in enumerate(zip(mats, ks))]
+    Xt = [torch_vec(X, torch.float32) for X in Xs]
+    Ys = [_empty_y(A, k) for A, k in zip(mats, ks)]
+    ctx.spmv_batch(list(zip(handles, Xt, Ys)))
+    torch.cuda.synchronize()
+    for Bo, X, Y, k in zip(B0, Xs, Ys, ks):
+        assert spmv_error(Bo, X, Y.cpu().numpy().astype(np.float64), "f32") <= TOL["f32"], k
+    # same products one at a time
+    for H, Bo, X, Xd, Y, k in zip(handles, B0, Xs, Xt, Ys, ks):
+        Ya = torch.empty_like(Y)
+        ctx.spmv(H, Xd, Ya)
+        torch.cuda.synchronize()
+        d = np.abs(Ya.cpu().numpy().astype(np.float64) - Y.cpu().numpy().astype(np.float64))
+        den = oracle.spmm(Bo.nrows, Bo.row_ptr, Bo.col, np.abs(Bo.val), np.abs(X))
+        den = den.reshape(d.shape)
+        assert np.all(d <= 2 * TOL["f32"] * np.where(den == 0, 1, den))
+
+
+def test_batch_plan_graph_replays(ctx):
+    """The plan's graph replays correctly several times, with eager work and
+    synchronisation between replays and with new X / Y buffers."""
+    mats = _pool(5, 200)
+    ks = [1, 4, 16, 2, 8]
+    handles = [ctx.permute(ctx.register(A, "f32"), 9) for A in mats]
+    B0 = []
+    for H, A in zip(handles, mats):
+        rperm, cperm = ctx.get_permutation(H)
+        B0.append(synth.CSR(A.nrows, A.ncols, *oracle.permute_csr(A, rperm, cperm)))
+    Xs = [_rand_x(A, k, 20 + i) for i, (A, k) in enumerate(zip(mats, ks))]
+    Xt = [torch_vec(X, torch.float32) for X in Xs]
+    Ys = [_empty_y(A, k) for A, k in zip(mats, ks)]
+    plan = ctx.batch_create(list(zip(handles, Xt, Ys)))
+    for replay in range(3):
+        for Y in Ys:
+            Y.fill_(float("nan"))
+        ctx.batch_launch(plan)
+        torch.cuda.synchronize()
+        _ = torch.ones(1000, device="cuda").sum().item()        # eager work between replays
+        for Bo, X, Y in zip(B0, Xs, Ys):
+            assert spmv_error(Bo, X, Y.cpu().numpy().astype(np.float64), "f32") <= TOL["f32"], replay
+    # new vectors: the descriptors are rewritten before the replay
+    Xs2 = [_rand_x(A, k, 30 + i) for i, (A, k) in enumerate(zip(mats, ks))]
+    Xt2 = [torch_vec(X, torch.float32) for X in Xs2]
+    Ys2 = [_empty_y(A, k) for A, k in zip(mats, ks)]
+    for _ in range(2):
+        ctx.batch_launch(plan, list(zip(handles, Xt2, Ys2)))
+        torch.cuda.synchronize()
+        for Bo, X, Y in zip(B0, Xs2, Ys2):
+            assert spmv_error(Bo, X, Y.cpu().numpy().astype(np.float64), "f32") <= TOL["f32"]
+    with pytest.raises(mx.MxeError):
+        ctx.batch_launch(plan, list(zip(handles[::-1], Xt2[::-1], Ys2[::-1])))
+    ctx.batch_destroy(plan)
+
+
+# --- serving ---------------------------------------------------------------------------
+
+def test_serving_mix_matches_alone(ctx):
+    mats = _pool(6, 300, rows=(20_000, 80_000))
+    handles = [ctx.permute(ctx.register(A, "f32"), 5) for A in mats]
+    rng = np.random.default_rng(1)
+    reqs = []
+    for r in range(64):
+        m = int(rng.integers(0, len(mats)))
+        k = int(rng.integers(1, 9))
+        flags = mx.SPACE_ORIGINAL if r % 3 == 0 else mx.SPACE_PERMUTED
+        X = _rand_x(mats[m], k, 1000 + r)
+        reqs.append((m, k, flags, X, torch_vec(X, torch.float32), _empty_y(mats[m], k)))
+    ctx.serve_start(streams=4, max_inflight=16, max_merge_k=16)
+    tickets = [None] * len(reqs)
+
+    def submitter(lo, hi):
+        for i in range(lo, hi):
+            m, k, flags, _, Xd, Y = reqs[i]
+            tickets[i] = ctx.submit(handles[m], Xd, Y, flags)
+
+    th = [threading.Thread(target=submitter, args=(i * 32, (i + 1) * 32)) for i in range(2)]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    lat = [ctx.wait(t) for t in tickets]
+    ctx.serve_stop()
+    assert all(v > 0 for v in lat)
+    for (m, k, flags, X, Xd, Y) in reqs:
+        Ya = torch.empty_like(Y)
+        ctx.spmv(handles[m], Xd, Ya, flags=flags)
+        torch.cuda.synchronize()
+        A = mats[m]
+        if flags == mx.SPACE_ORIGINAL:
+            ref_csr = A
+        else:
+            rperm, cperm = ctx.get_permutation(handles[m])
+            ref_csr = synth.CSR(A.nrows, A.ncols, *oracle.permute_csr(A, rperm, cperm))
+        y_mix = Y.cpu().numpy().astype(np.float64)
+        y_alone = Ya.cpu().numpy().astype(np.float64)
+        assert spmv_error(ref_csr, X, y_mix, "f32") <= TOL["f32"]
+        assert spmv_error(ref_csr, X, y_alone, "f32") <= TOL["f32"]
+
+
+def test_serving_budget_admission_and_busy_release(ctx):
+    A0 = synth.config2(1, n=200_000)
+    with mx.Context(0, budget_bytes=0) as probe:
+        H = probe.register(A0, "f32")
+        resident = probe.matrix_info(H).device_bytes
+    vec = 8 * (A0.nrows + A0.ncols) * 4            # one request of k = 8 in FP32
+    # room for the matrix and one in-flight request: requests run one at a time
+    with mx.Context(0, budget_bytes=resident + vec + 1024) as c2:
+        H = c2.register(A0, "f32")
+        c2.serve_start(streams=2, max_inflight=8, max_merge_k=1)
+        X = synth.vector(A0.ncols, 3, k=8)
+        Xd = torch_vec(X, torch.float32)
+        Ys = [torch.empty((A0.nrows, 8), dtype=torch.float32, device="cuda") for _ in range(6)]
+        ts = [c2.submit(H, Xd, Y) for Y in Ys]
+        with pytest.raises(mx.MxeError) as e:
+            c2.release(H)
+        assert e.value.status == mx.ERR_BUSY
+        for t in ts:
+            c2.wait(t)
+        for Y in Ys:
+            assert spmv_error(A0, X, Y.cpu().numpy().astype(np.float64), "f32") <= TOL["f32"]
+        # a request that can never fit the budget fails instead of waiting
+        X16 = torch_vec(synth.vector(A0.ncols, 4, k=16), torch.float32)
+        Y16 = torch.empty((A0.nrows, 16), dtype=torch.float32, device="cuda")
+        t = c2.submit(H, X16, Y16)
+        with pytest.raises(mx.MxeError) as e:
+            c2.wait(t)
+        assert e.value.status == mx.ERR_BUDGET
+        c2.serve_stop()
+        c2.release(H)
+
+
+def test_wait_timeout_and_unknown_ticket(ctx):
+    A0 = synth.config2(1, n=100_000)
+    H = ctx.register(A0, "f32")
+    ctx.serve_start(streams=1, max_inflight=1, max_merge_k=1)
+    X = torch_vec(synth.vector(A0.ncols, 3), torch.float32)
+    Y = torch.empty(A0.nrows, dtype=torch.float32, device="cuda")
+    t = ctx.submit(H, X, Y)
+    ctx.wait(t)
+    with pytest.raises(mx.MxeError) as e:
+        ctx.wait(t)                      # retired
+    assert e.value.status == mx.ERR_NOT_FOUND
+    ctx.serve_stop()
+    with pytest.raises(mx.MxeError):
+        ctx.submit(H, X, Y)              # loop stopped
+    ctx.release(H)
