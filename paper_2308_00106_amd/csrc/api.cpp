@@ -305,7 +305,8 @@ static mxe_status tune(mxe_ctx *ctx, Matrix &A, int32_t k, hipStream_t s, TuneRe
             best = ms;
             r.variant = v;
         }
-        if ((v & 0xf00) == MXE_VAR_GROUP && ms < best_group) {
+        // the persistent batch kernel runs multi-RHS items with lanes >= k class
+        if ((v & 0xf00) == MXE_VAR_GROUP && (v & 0xff) >= kc && ms < best_group) {
             best_group = ms;
             r.group_lanes = v & 0xff;
         }
@@ -850,7 +851,8 @@ static mxe_status build_descs(mxe_ctx *ctx, int32_t count, const mxe_item *items
         d.nrows = A->nrows;
         d.k = it.k;
         d.vtype = vtype_of(A->storage);
-        d.lanes = r.group_lanes;
+        d.kclass = kclass_of(it.k);
+        d.lanes = std::max(r.group_lanes, d.kclass);   // set_variant may force fewer
         d.rows_per_tile = (256 / r.group_lanes) * 4;
         d.tile_begin = (int32_t)tiles;
         tiles += (A->nrows + d.rows_per_tile - 1) / d.rows_per_tile;
@@ -859,6 +861,13 @@ static mxe_status build_descs(mxe_ctx *ctx, int32_t count, const mxe_item *items
     }
     total_tiles = (int32_t)tiles;
     return MXE_OK;
+}
+
+// the value type every item shares, or -1 (the persistent kernel then carries every path)
+static int common_vtype(const std::vector<BatchDesc> &descs) {
+    for (const BatchDesc &d : descs)
+        if (d.vtype != descs[0].vtype) return -1;
+    return descs.empty() ? -1 : descs[0].vtype;
 }
 
 mxe_status mxe_spmv_batch(mxe_ctx *ctx, int32_t count, const mxe_item *items, void *stream) {
@@ -877,7 +886,7 @@ mxe_status mxe_spmv_batch(mxe_ctx *ctx, int32_t count, const mxe_item *items, vo
     MXE_HIP(hipMemcpy(dd.p, descs.data(), sizeof(BatchDesc) * descs.size(), hipMemcpyHostToDevice));
     MXE_HIP(launch_batch_reset((int32_t *)ctr.p, s));
     MXE_HIP(launch_spmv_batch((const BatchDesc *)dd.p, count, total, (int32_t *)ctr.p,
-                              batch_grid_size(), s));
+                              batch_grid_size(), common_vtype(descs), s));
     return MXE_OK;
 }
 
@@ -898,7 +907,7 @@ mxe_status mxe_batch_create(mxe_ctx *ctx, int32_t count, const mxe_item *items, 
     MXE_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
     hipError_t e1 = launch_batch_reset(plan->counter, cs);
     hipError_t e2 = launch_spmv_batch(plan->descs_dev, count, plan->total_tiles, plan->counter,
-                                      batch_grid_size(), cs);
+                                      batch_grid_size(), common_vtype(plan->descs), cs);
     hipError_t e3 = hipStreamEndCapture(cs, &plan->graph);
     if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) {
         Plan &p = *plan;

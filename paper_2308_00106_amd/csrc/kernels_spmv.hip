@@ -102,6 +102,54 @@ __device__ inline void store_row(T *__restrict__ Y, int64_t ldy, int32_t row, in
     }
 }
 
+// Multi-RHS with column lanes (KM > 1, L >= KM): the row's L lanes are
+// KM column lanes times L/KM entry lanes. The KM lanes of one entry read its
+// value and column once (a broadcast) and the entry's X row as one contiguous
+// KM-wide access, so a gather costs one request instead of KM; each lane keeps
+// a single accumulator, reduced over the entry lanes of its column.
+template <typename V, typename T, int L, int KM>
+__device__ inline void row_product_cols(int32_t s, int32_t e, int lane,
+                                        const int32_t *__restrict__ col,
+                                        const V *__restrict__ val, int32_t k,
+                                        const T *__restrict__ X, int64_t ldx,
+                                        T *__restrict__ Y, int64_t ldy, int32_t row) {
+    constexpr int E = L / KM;
+    const int q = lane % KM, el = lane / KM;
+    const bool active = q < k;
+    T acc = T(0);
+    int32_t p = s + el;
+    for (; p + E < e; p += 2 * E) {            // two entries in flight per lane
+        const int32_t c0 = ld_stream(col + p), c1 = ld_stream(col + p + E);
+        const T a0 = ValLoad<V, T>::get(val + p), a1 = ValLoad<V, T>::get(val + p + E);
+        const T x0 = active ? X[(int64_t)c0 * ldx + q] : T(0);
+        const T x1 = active ? X[(int64_t)c1 * ldx + q] : T(0);
+        acc += a0 * x0;
+        acc += a1 * x1;
+    }
+    if (p < e) {
+        const int32_t c0 = ld_stream(col + p);
+        const T a0 = ValLoad<V, T>::get(val + p);
+        acc += a0 * (active ? X[(int64_t)c0 * ldx + q] : T(0));
+    }
+#pragma unroll
+    for (int off = L / 2; off >= KM; off >>= 1) acc += __shfl_xor(acc, off, L);
+    if (el == 0 && active) Y[(int64_t)row * ldy + q] = acc;
+}
+
+// One row's product by its group of L lanes, written to Y.
+template <typename V, typename T, int L, int KM>
+__device__ inline void row_product(int32_t s, int32_t e, int lane, const int32_t *__restrict__ col,
+                                   const V *__restrict__ val, int32_t k, const T *__restrict__ X,
+                                   int64_t ldx, T *__restrict__ Y, int64_t ldy, int32_t row) {
+    if constexpr (KM > 1 && L >= KM) {
+        row_product_cols<V, T, L, KM>(s, e, lane, col, val, k, X, ldx, Y, ldy, row);
+    } else {
+        T acc[KM];
+        row_dot<V, T, L, KM>(s, e, lane, col, val, k, X, ldx, acc);
+        store_row<T, L, KM>(Y, ldy, row, lane, k, acc);
+    }
+}
+
 // GROUP / BINNED: slot g (= global thread / L) computes row rows[g] (or g).
 template <typename V, typename T, int L, int KM>
 __global__ __launch_bounds__(kBlock) void k_spmv_group(
@@ -113,9 +161,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_group(
     if (slot >= count) return;                  // whole groups leave together
     const int32_t row = rows ? rows[slot] : (int32_t)slot;
     const int32_t s = ld_stream(rp + row), e = ld_stream(rp + row + 1);
-    T acc[KM];
-    row_dot<V, T, L, KM>(s, e, lane, col, val, k, X, ldx, acc);
-    store_row<T, L, KM>(Y, ldy, row, lane, k, acc);
+    row_product<V, T, L, KM>(s, e, lane, col, val, k, X, ldx, Y, ldy, row);
 }
 
 // ---- merge path -------------------------------------------------------------------
@@ -286,43 +332,46 @@ __global__ __launch_bounds__(kBlock) void k_merge_fixup(int32_t ntiles, const Ca
 
 // ---- batched persistent kernel -------------------------------------------------------
 
-template <typename V, typename T, int L, int KM>
-__device__ inline void batch_tile(const BatchDesc &d, int32_t r0, int32_t r1) {
-    const int lane = threadIdx.x % L;
-    for (int32_t row = r0 + threadIdx.x / L; row < r1; row += kBlock / L) {
-        const int32_t s = ld_stream(d.rp + row), e = ld_stream(d.rp + row + 1);
-        T acc[KM];
-        row_dot<V, T, L, KM>(s, e, lane, d.col, (const V *)d.val, d.k, (const T *)d.X, d.ldx,
-                             acc);
-        store_row<T, L, KM>((T *)d.Y, d.ldy, row, lane, d.k, acc);
-    }
-}
-
-template <typename V, typename T, int L>
-__device__ inline void batch_tile_k(const BatchDesc &d, int32_t r0, int32_t r1) {
-    if (d.k <= 1) batch_tile<V, T, L, 1>(d, r0, r1);
-    else if (d.k <= 2) batch_tile<V, T, L, 2>(d, r0, r1);
-    else if (d.k <= 4) batch_tile<V, T, L, 4>(d, r0, r1);
-    else if (d.k <= 8) batch_tile<V, T, L, 8>(d, r0, r1);
-    else batch_tile<V, T, L, 16>(d, r0, r1);
-}
-
+// One tile of a batch item with the lane count L and column count KM as
+// runtime values (KM = the item's k class, L >= KM, both powers of two): the
+// column-lane product above, one code path for every item, so the persistent
+// kernel needs the registers of a single accumulator. Groups are L-aligned, so
+// xor shuffles below L stay inside a group.
 template <typename V, typename T>
 __device__ inline void batch_tile_l(const BatchDesc &d, int32_t r0, int32_t r1) {
-    switch (d.lanes) {
-    case 1: batch_tile_k<V, T, 1>(d, r0, r1); break;
-    case 2: batch_tile_k<V, T, 2>(d, r0, r1); break;
-    case 4: batch_tile_k<V, T, 4>(d, r0, r1); break;
-    case 8: batch_tile_k<V, T, 8>(d, r0, r1); break;
-    case 16: batch_tile_k<V, T, 16>(d, r0, r1); break;
-    case 32: batch_tile_k<V, T, 32>(d, r0, r1); break;
-    default: batch_tile_k<V, T, 64>(d, r0, r1); break;
+    const int L = d.lanes, KM = d.kclass, E = L / KM;
+    const int lane = threadIdx.x % L, q = lane % KM, el = lane / KM;
+    const bool active = q < d.k;
+    const T *X = (const T *)d.X;
+    const V *val = (const V *)d.val;
+    for (int32_t row = r0 + threadIdx.x / L; row < r1; row += kBlock / L) {
+        const int32_t s = ld_stream(d.rp + row), e = ld_stream(d.rp + row + 1);
+        T acc = T(0);
+        int32_t p = s + el;
+        for (; p + E < e; p += 2 * E) {
+            const int32_t c0 = ld_stream(d.col + p), c1 = ld_stream(d.col + p + E);
+            const T a0 = ValLoad<V, T>::get(val + p), a1 = ValLoad<V, T>::get(val + p + E);
+            const T x0 = active ? X[(int64_t)c0 * d.ldx + q] : T(0);
+            const T x1 = active ? X[(int64_t)c1 * d.ldx + q] : T(0);
+            acc += a0 * x0;
+            acc += a1 * x1;
+        }
+        if (p < e) {
+            const int32_t c0 = ld_stream(d.col + p);
+            const T a0 = ValLoad<V, T>::get(val + p);
+            acc += a0 * (active ? X[(int64_t)c0 * d.ldx + q] : T(0));
+        }
+        for (int off = L / 2; off >= KM; off >>= 1) acc += __shfl_xor(acc, off);
+        if (el == 0 && active) ((T *)d.Y)[(int64_t)row * d.ldy + q] = acc;
     }
 }
 
 // Persistent grid: each workgroup takes the next tile index from a device
 // counter until all tiles of all matrices are done; every workgroup reaches
-// the exit test, so the grid always drains.
+// the exit test, so the grid always drains. VT is the value type shared by
+// every item, or -1 for a batch that mixes them (that instance carries every
+// path and so more registers).
+template <int VT>
 __global__ __launch_bounds__(kBlock) void k_spmv_batch(const BatchDesc *__restrict__ descs,
                                                        int32_t count, int32_t total_tiles,
                                                        int32_t *counter) {
@@ -342,9 +391,17 @@ __global__ __launch_bounds__(kBlock) void k_spmv_batch(const BatchDesc *__restri
         const BatchDesc d = descs[lo];
         const int32_t r0 = (tile - d.tile_begin) * d.rows_per_tile;
         const int32_t r1 = min(d.nrows, r0 + d.rows_per_tile);
-        if (d.vtype == VAL_F64) batch_tile_l<double, double>(d, r0, r1);
-        else if (d.vtype == VAL_F32) batch_tile_l<float, float>(d, r0, r1);
-        else batch_tile_l<uint16_t, float>(d, r0, r1);
+        if constexpr (VT == VAL_F64) {
+            batch_tile_l<double, double>(d, r0, r1);
+        } else if constexpr (VT == VAL_F32) {
+            batch_tile_l<float, float>(d, r0, r1);
+        } else if constexpr (VT == VAL_BF16) {
+            batch_tile_l<uint16_t, float>(d, r0, r1);
+        } else {
+            if (d.vtype == VAL_F64) batch_tile_l<double, double>(d, r0, r1);
+            else if (d.vtype == VAL_F32) batch_tile_l<float, float>(d, r0, r1);
+            else batch_tile_l<uint16_t, float>(d, r0, r1);
+        }
     }
 }
 
@@ -452,10 +509,25 @@ hipError_t launch_batch_reset(int32_t *counter, hipStream_t s) {
 int32_t batch_grid_size() { return 256 * 8; }   // 8 resident workgroups per CU
 
 hipError_t launch_spmv_batch(const BatchDesc *descs, int32_t count, int32_t total_tiles,
-                             int32_t *counter, int32_t grid, hipStream_t s) {
+                             int32_t *counter, int32_t grid, int vtype, hipStream_t s) {
     if (count <= 0 || total_tiles <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_spmv_batch, dim3(grid), dim3(kBlock), 0, s, descs, count, total_tiles,
-                       counter);
+    switch (vtype) {
+    case VAL_F64:
+        hipLaunchKernelGGL(k_spmv_batch<VAL_F64>, dim3(grid), dim3(kBlock), 0, s, descs, count,
+                           total_tiles, counter);
+        break;
+    case VAL_F32:
+        hipLaunchKernelGGL(k_spmv_batch<VAL_F32>, dim3(grid), dim3(kBlock), 0, s, descs, count,
+                           total_tiles, counter);
+        break;
+    case VAL_BF16:
+        hipLaunchKernelGGL(k_spmv_batch<VAL_BF16>, dim3(grid), dim3(kBlock), 0, s, descs, count,
+                           total_tiles, counter);
+        break;
+    default:
+        hipLaunchKernelGGL(k_spmv_batch<-1>, dim3(grid), dim3(kBlock), 0, s, descs, count,
+                           total_tiles, counter);
+    }
     return hipGetLastError();
 }
 

@@ -60,7 +60,7 @@ struct Server {
 
     void run();
     void retire_done();
-    bool admit_one();
+    bool admit_one(std::unique_lock<std::mutex> &lk);
     mxe_status issue(std::vector<std::shared_ptr<Request>> &group, hipStream_t s);
 };
 
@@ -137,7 +137,7 @@ mxe_status Server::issue(std::vector<std::shared_ptr<Request>> &group, hipStream
 
 // Admits the head of the queue (plus mergeable requests) if a slot and the
 // budget allow it. Returns false when nothing more can be admitted now.
-bool Server::admit_one() {
+bool Server::admit_one(std::unique_lock<std::mutex> &lk) {
     if (queue.empty() || inflight_reqs >= cfg.max_inflight) return false;
     std::shared_ptr<Request> head = queue.front();
     std::vector<std::shared_ptr<Request>> group{head};
@@ -178,11 +178,11 @@ bool Server::admit_one() {
             }
     hipStream_t s = streams[next_stream];
     next_stream = (next_stream + 1) % (int)streams.size();
-    mxe_status st;
-    {
-        std::lock_guard<std::recursive_mutex> lk(ctx->mu);
-        st = issue(group, s);
-    }
+    // reserve the slots and bytes, then issue without holding the queue lock
+    // so submitters are not blocked by the device calls
+    for (auto &r : group) r->state = 1;
+    inflight_reqs += (int)group.size();
+    inflight_bytes += bytes;
     hipEvent_t ev = nullptr;
     if (!free_events.empty()) {
         ev = free_events.back();
@@ -190,16 +190,23 @@ bool Server::admit_one() {
     } else if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
         ev = nullptr;
     }
-    if (st == MXE_OK && ev && hipEventRecord(ev, s) == hipSuccess) {
+    lk.unlock();
+    mxe_status st;
+    {
+        std::lock_guard<std::recursive_mutex> clk(ctx->mu);
+        st = issue(group, s);
+    }
+    const bool recorded = st == MXE_OK && ev && hipEventRecord(ev, s) == hipSuccess;
+    lk.lock();
+    if (recorded) {
         Launch l;
         l.reqs = group;
         l.ev = ev;
         l.bytes = bytes;
-        for (auto &r : group) r->state = 1;
-        inflight_reqs += (int)group.size();
-        inflight_bytes += bytes;
         inflight.push_back(std::move(l));
     } else {
+        inflight_reqs -= (int)group.size();
+        inflight_bytes -= bytes;
         if (ev) free_events.push_back(ev);
         const auto now = Clock::now();
         for (auto &r : group) {
@@ -219,7 +226,7 @@ void Server::run() {
     std::unique_lock<std::mutex> lk(mu);
     for (;;) {
         retire_done();
-        while (admit_one()) {
+        while (admit_one(lk)) {
         }
         if (stop && queue.empty() && inflight.empty()) break;
         if (inflight.empty() && queue.empty()) {
