@@ -65,6 +65,7 @@ typedef enum mxe_dtype {        /* storage type of matrix values */
 #define MXE_OUTPUT_DEVICE   0x1u  /* get_permutation / export: outputs are device pointers */
 #define MXE_ROWS            0x1u  /* permute mode: random row permutation ("R") */
 #define MXE_COLS            0x2u  /* permute mode: random column permutation */
+#define MXE_GRADIENT        0x4u  /* permute mode: gradient-based shuffles (G-R, G-C) */
 #define MXE_SPACE_PERMUTED  0x0u  /* spmv: X, Y are in the permuted index space */
 #define MXE_SPACE_ORIGINAL  0x1u  /* spmv: X, Y are in A's index space (gather/scatter inside) */
 
@@ -122,7 +123,14 @@ mxe_status mxe_register_matrix(mxe_ctx *ctx, int32_t nrows, int32_t ncols, int64
  * 64-bit keys, key(i) = i-th output of SplitMix64 started at the stream seed;
  * the row stream's seed is the first SplitMix64 output started at `seed`, the
  * column stream's the second. Equal seeds give bit-identical B. B's rows are
- * re-sorted by new column; values move bit-exactly. B holds A alive. */
+ * re-sorted by new column; values move bit-exactly. B holds A alive.
+ * With MXE_GRADIENT the rows (MXE_ROWS) and/or columns (MXE_COLS) take
+ * Section 8's gradient formats instead (G-R, G-C): with h the nonzeros per
+ * row (per column), the pivot p is the first index of the maximum of
+ * h[i+1] - h[i]; the parts [0, p] and [p+1, n) are each ordered by the
+ * stream's keys (random order within each part) and riffled, the two parts
+ * alternating and the longer part's remainder appended. Synchronizes
+ * `stream` once per gradient shuffle (the pivot sizes the parts). */
 mxe_status mxe_permute(mxe_ctx *ctx, mxe_mat a, uint64_t seed, uint32_t mode,
                        void *stream, mxe_mat *out_b);
 
@@ -158,6 +166,19 @@ mxe_status mxe_release(mxe_ctx *ctx, mxe_mat m);
 mxe_status mxe_entropy(mxe_ctx *ctx, mxe_mat m, int32_t grid_rows, int32_t grid_cols,
                        void *stream, double *h_bits, double *h_nats, int64_t *hist);
 
+/* Hierarchical 2D entropy (Section 5: 2x2, 4x4 and 8x8 heat maps, fewer
+ * regions where the grid is smaller). For each of the nlevels levels L the
+ * grid_rows x grid_cols block histogram is cut into Lr x Lc regions,
+ * Lr = min(L, grid_rows), Lc = min(L, grid_cols); region (a, b) holds the
+ * bins (r, c) with floor(r*Lr/grid_rows) = a and floor(c*Lc/grid_cols) = b,
+ * and its entropy is that of its own bins, correctly rounded as in
+ * mxe_entropy. h_bits / h_nats (host, nats may be NULL) receive the levels
+ * one after another, each Lr x Lc row-major. 1 <= L <= 64. Synchronizes.
+ * Returns MXE_ERR_INEXACT (values written) if any rounding is uncertified. */
+mxe_status mxe_entropy_levels(mxe_ctx *ctx, mxe_mat m, int32_t grid_rows, int32_t grid_cols,
+                              const int32_t *levels, int32_t nlevels, void *stream,
+                              double *h_bits, double *h_nats);
+
 /* --- products (Section 2) --------------------------------------------------- */
 
 /* Y = M X for one matrix, k >= 1 right-hand sides (X: ncols x k, Y: nrows x k).
@@ -186,6 +207,10 @@ mxe_status mxe_scatter_y(mxe_ctx *ctx, mxe_mat b, int32_t k, const void *Yp, int
 #define MXE_VAR_BINNED  0x100
 #define MXE_VAR_MERGE   0x200
 #define MXE_VAR_SLAB    0x300
+/* MXE_VAR_FIXED with lanes per row (1..64): Section 7's equal-row split, a
+ * fixed grid of 2048 workgroups each owning an equal contiguous share of rows,
+ * nothing rebalanced (the case where the paper sees randomization help). */
+#define MXE_VAR_FIXED   0x400
 #define MXE_VARIANT(family, lanes) ((family) | (lanes))
 
 /* Times the candidate variants for (m, k) on the device and caches the

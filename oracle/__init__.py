@@ -177,6 +177,72 @@ def entropy(hist) -> tuple[float, float]:
     return float(bits), float(nats)
 
 
+def entropy_levels(hist, levels=(2, 4, 8)):
+    """Hierarchical 2D entropy (Section 5): for each level L the G_r x G_c
+    histogram is cut into min(L, G_r) x min(L, G_c) regions, region (a, b)
+    holding the bins (r, c) with floor(r * Lr / G_r) = a and
+    floor(c * Lc / G_c) = b, and each region's entropy is that of its own
+    bins (Eq. 2). Returns a list of (bits, nats) arrays of shape [Lr, Lc]."""
+    h = np.asarray(hist, dtype=np.int64)
+    gr, gc = h.shape
+    out = []
+    for L in levels:
+        lr, lc = min(L, gr), min(L, gc)
+        bits = np.zeros((lr, lc))
+        nats = np.zeros((lr, lc))
+        for a in range(lr):
+            rows = [r for r in range(gr) if r * lr // gr == a]
+            for b in range(lc):
+                cols = [c for c in range(gc) if c * lc // gc == b]
+                bits[a, b], nats[a, b] = entropy(h[np.ix_(rows, cols)])
+        out.append((bits, nats))
+    return out
+
+
+# --- gradient-based shuffle (Sections 5 and 8) ---------------------------------
+
+def gradient_permutation(counts, stream_seed: int) -> np.ndarray:
+    """G-R / G-C shuffle of n items with per-item nonzero counts h (row
+    lengths, or column counts): the gradient g_i = h_{i+1} - h_i, the pivot
+    p = first index of its maximum, the parts A = [0, p] and B = [p+1, n);
+    each part is permuted at random (the stable order of the stream's keys
+    restricted to that part) and the two are riffled like a deck of cards,
+    A and B alternating and the longer part's remainder appended. Returns the
+    new-to-old permutation."""
+    h = np.asarray(counts, dtype=np.int64)
+    n = len(h)
+    if n < 2:
+        return np.arange(n, dtype=np.int32)
+    g = h[1:] - h[:-1]
+    p = int(np.argmax(g))
+    keys = splitmix64_outputs(stream_seed, n)
+    A = np.arange(0, p + 1)
+    B = np.arange(p + 1, n)
+    A = A[np.argsort(keys[A], kind="stable")]
+    B = B[np.argsort(keys[B], kind="stable")]
+    m = min(len(A), len(B))
+    out = np.empty(n, dtype=np.int64)
+    out[0:2 * m:2] = A[:m]
+    out[1:2 * m:2] = B[:m]
+    out[2 * m:] = A[m:] if len(A) > m else B[m:]
+    return out.astype(np.int32)
+
+
+GRADIENT = 4
+
+
+def permute_gradient(A, seed: int, mode: int = ROWS | GRADIENT):
+    """Section 8's gradient formats: rows by the gradient shuffle when mode
+    has ROWS (G-R), columns too when it has COLS (G-C). Returns
+    (rperm, cperm, (rp, col, val))."""
+    s_r, s_c = stream_seeds(seed)
+    rperm = (gradient_permutation(A.row_lengths(), s_r) if mode & ROWS
+             else np.arange(A.nrows, dtype=np.int32))
+    cperm = (gradient_permutation(np.bincount(A.col, minlength=A.ncols), s_c) if mode & COLS
+             else np.arange(A.ncols, dtype=np.int32))
+    return rperm, cperm, permute_csr(A, rperm, cperm)
+
+
 # --- SpMV / SpMM (Section 2) ------------------------------------------------
 
 def spmm(nrows: int, row_ptr, col, val, X: np.ndarray) -> np.ndarray:

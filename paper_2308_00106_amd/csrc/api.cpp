@@ -261,6 +261,7 @@ static mxe_status tune(mxe_ctx *ctx, Matrix &A, int32_t k, hipStream_t s, TuneRe
     std::vector<int> cands;
     for (int l = 1; l <= 64; l <<= 1) cands.push_back(MXE_VARIANT(MXE_VAR_GROUP, l));
     cands.push_back(MXE_VARIANT(MXE_VAR_BINNED, 0));
+    cands.push_back(MXE_VARIANT(MXE_VAR_FIXED, std::max(kc, 8)));
     if (kc <= 4) cands.push_back(MXE_VARIANT(MXE_VAR_MERGE, 0));
     for (int units : {16, 32, 64}) {                 // 1, 2 and 4 MiB of x per slab
         SlabGeom g;
@@ -532,10 +533,13 @@ mxe_status mxe_register_matrix(mxe_ctx *ctx, int32_t nrows, int32_t ncols, int64
     return MXE_OK;
 }
 
+// per-line nonzero counts ahead of the gradient shuffle's own workspace
+static size_t counts_bytes(int64_t n) { return (4 * ((size_t)n + 64) + 255) & ~size_t(255); }
+
 mxe_status mxe_permute(mxe_ctx *ctx, mxe_mat a, uint64_t seed, uint32_t mode, void *stream,
                        mxe_mat *out_b) {
     if (!ctx || !out_b) return fail(MXE_ERR_INVALID_ARG, "ctx or out_b is NULL");
-    if (mode & ~(MXE_ROWS | MXE_COLS)) return fail(MXE_ERR_INVALID_ARG, "unknown mode bits");
+    if (mode & ~(MXE_ROWS | MXE_COLS | MXE_GRADIENT)) return fail(MXE_ERR_INVALID_ARG, "unknown mode bits");
     std::lock_guard<std::recursive_mutex> lk(ctx->mu);
     DeviceGuard g(ctx->device);
     auto A = find_matrix(ctx, a);
@@ -573,16 +577,33 @@ mxe_status mxe_permute(mxe_ctx *ctx, mxe_mat a, uint64_t seed, uint32_t mode, vo
     // stream seeds: first and second SplitMix64 outputs started at `seed`
     const uint64_t s_row = sm64_key(seed, 0), s_col = sm64_key(seed, 1);
     Scratch ws;
-    const size_t ws_bytes = std::max({random_perm_ws_bytes(M), random_perm_ws_bytes(N),
-                                      permuted_row_ptr_ws_bytes(M)});
+    const bool grad = mode & MXE_GRADIENT;
+    size_t ws_bytes = std::max({random_perm_ws_bytes(M), random_perm_ws_bytes(N),
+                                permuted_row_ptr_ws_bytes(M)});
+    if (grad)
+        ws_bytes = std::max({ws_bytes, gradient_perm_ws_bytes(M) + counts_bytes(M),
+                             gradient_perm_ws_bytes(N) + counts_bytes(N)});
     if ((st = ws.alloc(ws_bytes, s))) return st;
-    if (mode & MXE_ROWS) {
+    // gradient formats (Section 8, G-R and G-C): per-line counts go first in
+    // the workspace, the shuffle's own workspace after them
+    auto gradient = [&](bool rows, int32_t n, uint64_t seed_n, int32_t *perm, int32_t *inv) {
+        int32_t *counts = (int32_t *)ws.p;
+        void *gws = (char *)ws.p + counts_bytes(n);
+        hipError_t e = launch_line_counts(rows, M, A->nnz, A->rp, A->col, n, counts, s);
+        if (e == hipSuccess) e = launch_gradient_perm(n, counts, seed_n, perm, inv, gws, s);
+        return e;
+    };
+    if ((mode & MXE_ROWS) && grad) {
+        MXE_HIP(gradient(true, M, s_row, B->rperm, B->rinv));
+    } else if (mode & MXE_ROWS) {
         MXE_HIP(launch_random_perm(M, s_row, B->rperm, B->rinv, ws.p, s));
     } else {
         MXE_HIP(launch_iota_i32(B->rperm, M, s));
         MXE_HIP(launch_iota_i32(B->rinv, M, s));
     }
-    if (mode & MXE_COLS) {
+    if ((mode & MXE_COLS) && grad) {
+        MXE_HIP(gradient(false, N, s_col, B->cperm, B->cinv));
+    } else if (mode & MXE_COLS) {
         MXE_HIP(launch_random_perm(N, s_col, B->cperm, B->cinv, ws.p, s));
     } else {
         MXE_HIP(launch_iota_i32(B->cperm, N, s));
@@ -715,6 +736,50 @@ mxe_status mxe_entropy(mxe_ctx *ctx, mxe_mat m, int32_t grid_rows, int32_t grid_
     return MXE_OK;
 }
 
+mxe_status mxe_entropy_levels(mxe_ctx *ctx, mxe_mat m, int32_t grid_rows, int32_t grid_cols,
+                              const int32_t *levels, int32_t nlevels, void *stream,
+                              double *h_bits, double *h_nats) {
+    if (!ctx || !h_bits || !levels) return fail(MXE_ERR_INVALID_ARG, "ctx, levels or h_bits is NULL");
+    if (grid_rows < 1 || grid_cols < 1 || grid_rows > (1 << 20) || grid_cols > (1 << 20))
+        return fail(MXE_ERR_INVALID_ARG, "grid dimensions must lie in [1, 2^20]");
+    const int64_t bins = (int64_t)grid_rows * grid_cols;
+    if (bins > (int64_t(1) << 30)) return fail(MXE_ERR_INVALID_ARG, "more than 2^30 bins");
+    if (nlevels < 1 || nlevels > 16) return fail(MXE_ERR_INVALID_ARG, "1..16 levels");
+    for (int32_t i = 0; i < nlevels; ++i)
+        if (levels[i] < 1 || levels[i] > 64) return fail(MXE_ERR_INVALID_ARG, "levels must lie in [1, 64]");
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    DeviceGuard g(ctx->device);
+    auto A = find_matrix(ctx, m);
+    if (!A) return fail(MXE_ERR_NOT_FOUND, "unknown matrix handle");
+    const int32_t nreg = entropy_regions_count(grid_rows, grid_cols, levels, nlevels);
+    if (A->nnz == 0) {
+        std::fill(h_bits, h_bits + nreg, 0.0);
+        if (h_nats) std::fill(h_nats, h_nats + nreg, 0.0);
+        return MXE_OK;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    Scratch hdev, ws, res;
+    mxe_status st;
+    if ((st = hdev.alloc(4 * (size_t)bins, s))) return st;
+    if ((st = ws.alloc(entropy_regions_ws_bytes(nreg), s))) return st;
+    if ((st = res.alloc(4 * sizeof(double) * (size_t)nreg, s))) return st;
+    MXE_HIP(launch_block_hist(A->nrows, A->ncols, A->nnz, A->rp, A->col, grid_rows, grid_cols,
+                              (uint32_t *)hdev.p, s));
+    MXE_HIP(launch_entropy_regions((const uint32_t *)hdev.p, grid_rows, grid_cols, levels, nlevels,
+                                   (double *)res.p, ws.p, s));
+    std::vector<double> r(4 * (size_t)nreg);
+    MXE_HIP(hipMemcpyAsync(r.data(), res.p, sizeof(double) * r.size(), hipMemcpyDeviceToHost, s));
+    MXE_HIP(hipStreamSynchronize(s));
+    bool ok = true;
+    for (int32_t i = 0; i < nreg; ++i) {
+        h_bits[i] = r[4 * (size_t)i];
+        if (h_nats) h_nats[i] = r[4 * (size_t)i + 1];
+        ok = ok && r[4 * (size_t)i + 2] == 1.0;
+    }
+    if (!ok) return fail(MXE_ERR_INEXACT, "entropy rounding could not be certified");
+    return MXE_OK;
+}
+
 static mxe_status check_dense(const Matrix &A, int32_t k, const void *X, int64_t ldx,
                               const void *Y, int64_t ldy) {
     if (k < 1) return fail(MXE_ERR_INVALID_ARG, "k must be >= 1");
@@ -802,9 +867,10 @@ mxe_status mxe_set_variant(mxe_ctx *ctx, mxe_mat m, int32_t k, int32_t variant) 
     }
     const int family = variant & 0xf00, lanes = variant & 0xff;
     const bool pow2 = lanes >= 1 && lanes <= 64 && (lanes & (lanes - 1)) == 0;
-    if (family == MXE_VAR_GROUP && !pow2) return fail(MXE_ERR_INVALID_ARG, "lanes must be 1..64, a power of two");
+    if ((family == MXE_VAR_GROUP || family == MXE_VAR_FIXED) && !pow2)
+        return fail(MXE_ERR_INVALID_ARG, "lanes must be 1..64, a power of two");
     if (family != MXE_VAR_GROUP && family != MXE_VAR_BINNED && family != MXE_VAR_MERGE &&
-        family != MXE_VAR_SLAB)
+        family != MXE_VAR_SLAB && family != MXE_VAR_FIXED)
         return fail(MXE_ERR_INVALID_ARG, "unknown variant family");
     if (family == MXE_VAR_SLAB) {
         SlabGeom sg;

@@ -24,6 +24,17 @@ size_t random_perm_ws_bytes(int64_t n);
 hipError_t launch_random_perm(int64_t n, uint64_t stream_seed, int32_t *perm, int32_t *inv,
                               void *ws, hipStream_t s);
 
+// ---- gradient-based shuffle --------------------------------------------------
+// counts[i] = nonzeros of row i (rows) or of column i (!rows, n = ncols).
+hipError_t launch_line_counts(bool rows, int32_t nrows, int64_t nnz, const int32_t *rp,
+                              const int32_t *col, int32_t n, int32_t *counts, hipStream_t s);
+// Pivot at the first maximum of counts[i+1] - counts[i], random permutation
+// of each part, riffle. Synchronizes s once (the pivot sizes the parts).
+// Workspace: gradient_perm_ws_bytes(n).
+size_t gradient_perm_ws_bytes(int64_t n);
+hipError_t launch_gradient_perm(int64_t n, const int32_t *counts, uint64_t stream_seed,
+                                int32_t *perm, int32_t *inv, void *ws, hipStream_t s);
+
 // ---- permuted CSR --------------------------------------------------------
 // rp_b[i'] = exclusive prefix of A's row lengths taken in rperm order.
 // Workspace: permuted_row_ptr_ws_bytes(nrows).
@@ -73,6 +84,15 @@ hipError_t launch_block_hist(int32_t nrows, int32_t ncols, int64_t nnz, const in
 size_t entropy_ws_bytes(int64_t bins);
 hipError_t launch_entropy(const uint32_t *hist, int64_t bins, double *result, void *ws,
                           hipStream_t s);
+// Hierarchical entropy: for each level L, min(L, G_r) x min(L, G_c) regions;
+// result holds 4 doubles per region (as launch_entropy), levels in order,
+// regions row-major. Synchronizes s (the region table is staged from the host).
+int32_t entropy_regions_count(int32_t grid_r, int32_t grid_c, const int32_t *levels,
+                              int32_t nlevels);
+size_t entropy_regions_ws_bytes(int32_t nregions);
+hipError_t launch_entropy_regions(const uint32_t *hist, int32_t grid_r, int32_t grid_c,
+                                  const int32_t *levels, int32_t nlevels, double *result,
+                                  void *ws, hipStream_t s);
 
 // ---- SpMV / SpMM ------------------------------------------------------------
 enum ValType { VAL_F64 = 0, VAL_F32 = 1, VAL_BF16 = 2 };

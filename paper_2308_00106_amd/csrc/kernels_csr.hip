@@ -191,7 +191,7 @@ __global__ __launch_bounds__(kBlock) void k_bucket_rank(int64_t nbuckets, uint64
         }
         if (valid) {
             perm[o + rank] = idx;
-            inv[idx] = o + rank;
+            if (inv) inv[idx] = o + rank;
         }
     }
 }
@@ -364,6 +364,79 @@ __global__ void k_bin_bounds(const int32_t *off, int32_t nwg, int32_t nrows, int
     if (b == kNumBins) bin_off[b] = nrows;
 }
 
+// ---- gradient-based shuffle (Sections 5 and 8) -------------------------------------
+
+__global__ __launch_bounds__(kBlock) void k_row_counts(int32_t nrows, const int32_t *rp,
+                                                       int32_t *counts) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nrows;
+         i += (int64_t)gridDim.x * blockDim.x)
+        counts[i] = rp[i + 1] - rp[i];
+}
+
+__global__ __launch_bounds__(kBlock) void k_col_counts(int64_t nnz, const int32_t *col,
+                                                       int32_t *counts) {
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < nnz;
+         e += (int64_t)gridDim.x * blockDim.x)
+        atomicAdd(&counts[col[e]], 1);
+}
+
+struct ArgMax { int64_t g; int64_t i; };
+
+__device__ inline ArgMax better(ArgMax a, ArgMax b) {        // larger g; first index on ties
+    return (b.g > a.g || (b.g == a.g && b.i < a.i)) ? b : a;
+}
+
+__device__ inline ArgMax block_argmax(ArgMax v, ArgMax *sh) {
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) sh[threadIdx.x] = better(sh[threadIdx.x], sh[threadIdx.x + w]);
+        __syncthreads();
+    }
+    return sh[0];
+}
+
+// gradient g_i = h[i+1] - h[i], i < n - 1 (n >= 2)
+__global__ __launch_bounds__(kBlock) void k_grad_argmax_partial(int64_t n, const int32_t *h,
+                                                                ArgMax *part) {
+    __shared__ ArgMax sh[kBlock];
+    ArgMax best{INT64_MIN, INT64_MAX};
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n - 1;
+         i += (int64_t)gridDim.x * blockDim.x)
+        best = better(best, ArgMax{(int64_t)h[i + 1] - h[i], i});
+    best = block_argmax(best, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = best;
+}
+
+__global__ __launch_bounds__(kBlock) void k_grad_argmax_final(int32_t nparts, const ArgMax *part,
+                                                              int32_t *pivot) {
+    __shared__ ArgMax sh[kBlock];
+    ArgMax best{INT64_MIN, INT64_MAX};
+    for (int i = threadIdx.x; i < nparts; i += kBlock) best = better(best, part[i]);
+    best = block_argmax(best, sh);
+    if (threadIdx.x == 0) *pivot = (int32_t)best.i;
+}
+
+// Riffle: A (local permutation pa of [0, na)) and B (pb of [0, nb), offset
+// by na) alternate while both last; the longer part's remainder follows.
+__global__ __launch_bounds__(kBlock) void k_riffle(int64_t na, int64_t nb, const int32_t *pa,
+                                                   const int32_t *pb, int32_t *perm) {
+    const int64_t m = na < nb ? na : nb, n = na + nb;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        int32_t v;
+        if (t < 2 * m) v = (t & 1) ? (int32_t)(na + pb[t >> 1]) : pa[t >> 1];
+        else v = na > m ? pa[m + (t - 2 * m)] : (int32_t)(na + pb[m + (t - 2 * m)]);
+        perm[t] = v;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_invert(int64_t n, const int32_t *perm, int32_t *inv) {
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n;
+         k += (int64_t)gridDim.x * blockDim.x)
+        inv[perm[k]] = (int32_t)k;
+}
+
 }  // namespace
 
 // ============================ launchers ==========================================
@@ -514,6 +587,61 @@ hipError_t launch_convert_f64(const double *in, void *out, int64_t n, int dtype,
         hipLaunchKernelGGL(k_f64_to_bf16, dim3(g), dim3(kBlock), 0, s, in, (uint16_t *)out, n);
     else
         return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_line_counts(bool rows, int32_t nrows, int64_t nnz, const int32_t *rp,
+                              const int32_t *col, int32_t n, int32_t *counts, hipStream_t s) {
+    if (rows) {
+        if (nrows <= 0) return hipSuccess;
+        hipLaunchKernelGGL(k_row_counts, dim3(grid_for(nrows, kBlock, 16384)), dim3(kBlock), 0, s,
+                           nrows, rp, counts);
+        return hipGetLastError();
+    }
+    hipError_t e = launch_fill_i32(counts, n, 0, s);
+    if (e != hipSuccess || nnz <= 0) return e;
+    hipLaunchKernelGGL(k_col_counts, dim3(grid_for(nnz, kBlock, 16384)), dim3(kBlock), 0, s, nnz,
+                       col, counts);
+    return hipGetLastError();
+}
+
+namespace {
+constexpr int kArgParts = 1024;
+}
+
+size_t gradient_perm_ws_bytes(int64_t n) {
+    return align256(sizeof(ArgMax) * kArgParts) + 256 + align256(sizeof(int32_t) * (n + 1)) +
+           random_perm_ws_bytes(n);
+}
+
+hipError_t launch_gradient_perm(int64_t n, const int32_t *counts, uint64_t stream_seed,
+                                int32_t *perm, int32_t *inv, void *ws, hipStream_t s) {
+    if (n < 2) {
+        hipError_t e = launch_iota_i32(perm, n, s);
+        return e != hipSuccess ? e : launch_iota_i32(inv, n, s);
+    }
+    char *w = (char *)ws;
+    ArgMax *part = (ArgMax *)w;  w += align256(sizeof(ArgMax) * kArgParts);
+    int32_t *pivot = (int32_t *)w;  w += 256;
+    int32_t *pab = (int32_t *)w;  w += align256(sizeof(int32_t) * (n + 1));
+    void *rws = w;
+    const int g = grid_for(n - 1, kBlock, kArgParts);
+    hipLaunchKernelGGL(k_grad_argmax_partial, dim3(g), dim3(kBlock), 0, s, n, counts, part);
+    hipLaunchKernelGGL(k_grad_argmax_final, dim3(1), dim3(kBlock), 0, s, g, (const ArgMax *)part,
+                       pivot);
+    int32_t p = 0;
+    hipError_t e = hipMemcpyAsync(&p, pivot, sizeof p, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);     // the pivot sizes the two parts
+    if (e != hipSuccess) return e;
+    const int64_t na = (int64_t)p + 1, nb = n - na;
+    // part B's keys continue the stream at index na: key(s, na + i) = key(s + na*gamma, i)
+    const uint64_t seed_b = stream_seed + (uint64_t)na * 0x9e3779b97f4a7c15ull;
+    if ((e = launch_random_perm(na, stream_seed, pab, nullptr, rws, s)) != hipSuccess) return e;
+    if ((e = launch_random_perm(nb, seed_b, pab + na, nullptr, rws, s)) != hipSuccess) return e;
+    const int gr = grid_for(n, kBlock, 16384);
+    hipLaunchKernelGGL(k_riffle, dim3(gr), dim3(kBlock), 0, s, na, nb, (const int32_t *)pab,
+                       (const int32_t *)(pab + na), perm);
+    hipLaunchKernelGGL(k_invert, dim3(gr), dim3(kBlock), 0, s, n, (const int32_t *)perm, inv);
     return hipGetLastError();
 }
 

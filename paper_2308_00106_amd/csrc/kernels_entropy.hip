@@ -17,6 +17,9 @@
 #include "device_common.h"
 #include "internal.h"
 
+#include <algorithm>
+#include <vector>
+
 namespace mxe {
 
 namespace {
@@ -162,22 +165,11 @@ __device__ inline double certified_round(dd v, double eps, int *ok) {
     return v.hi + v.lo;
 }
 
-__global__ __launch_bounds__(kBlock) void k_entropy_final(const EntPartial *part, int nparts,
-                                                          double *result) {
-    __shared__ dd coef[kLnTerms];
-    __shared__ dd ln2;
-    __shared__ dd sh[kBlock];
-    __shared__ unsigned long long ss[kBlock], sz[kBlock];
-    setup_log_tables(coef, &ln2);
-    dd acc{0.0, 0.0};
-    unsigned long long s = 0, nz = 0;
-    for (int i = threadIdx.x; i < nparts; i += kBlock) {
-        acc = dd_add(acc, dd{part[i].hi, part[i].lo});
-        s += part[i].s;
-        nz += part[i].nz;
-    }
-    block_reduce(acc, s, nz, sh, ss, sz);
-    if (threadIdx.x != 0) return;
+// From T = sum h ln h (double-double), S = sum h and the count of nonzero
+// bins: result = {H bits, H nats, certified (1/0), S}, each H rounded to FP64
+// and certified against the error bound (Eq. 2 with p = h / S).
+__device__ inline void entropy_finish(dd acc, unsigned long long s, unsigned long long nz, dd ln2,
+                                      const dd *coef, double *result) {
     if (s == 0 || nz <= 1) {            // no distribution, or all mass in one bin
         result[0] = 0.0;
         result[1] = 0.0;
@@ -198,6 +190,54 @@ __global__ __launch_bounds__(kBlock) void k_entropy_final(const EntPartial *part
     result[1] = certified_round(h_nats, eps, &ok);
     result[2] = ok ? 1.0 : 0.0;
     result[3] = sd;
+}
+
+__global__ __launch_bounds__(kBlock) void k_entropy_final(const EntPartial *part, int nparts,
+                                                          double *result) {
+    __shared__ dd coef[kLnTerms];
+    __shared__ dd ln2;
+    __shared__ dd sh[kBlock];
+    __shared__ unsigned long long ss[kBlock], sz[kBlock];
+    setup_log_tables(coef, &ln2);
+    dd acc{0.0, 0.0};
+    unsigned long long s = 0, nz = 0;
+    for (int i = threadIdx.x; i < nparts; i += kBlock) {
+        acc = dd_add(acc, dd{part[i].hi, part[i].lo});
+        s += part[i].s;
+        nz += part[i].nz;
+    }
+    block_reduce(acc, s, nz, sh, ss, sz);
+    if (threadIdx.x == 0) entropy_finish(acc, s, nz, ln2, coef, result);
+}
+
+// Hierarchical 2D entropy (Section 5): one workgroup per region of one
+// level; region r covers bins [r0, r1) x [c0, c1) of the grid.
+struct Region { int32_t r0, r1, c0, c1; };
+
+__global__ __launch_bounds__(kBlock) void k_entropy_regions(const uint32_t *__restrict__ hist,
+                                                            int32_t grid_c,
+                                                            const Region *__restrict__ regions,
+                                                            double *__restrict__ out) {
+    __shared__ dd coef[kLnTerms];
+    __shared__ dd ln2;
+    __shared__ dd sh[kBlock];
+    __shared__ unsigned long long ss[kBlock], sz[kBlock];
+    setup_log_tables(coef, &ln2);
+    const Region rg = regions[blockIdx.x];
+    const int64_t w = rg.c1 - rg.c0, cells = (int64_t)(rg.r1 - rg.r0) * w;
+    dd acc{0.0, 0.0};
+    unsigned long long s = 0, nz = 0;
+    for (int64_t i = threadIdx.x; i < cells; i += kBlock) {
+        const uint32_t h = hist[(int64_t)(rg.r0 + i / w) * grid_c + rg.c0 + i % w];
+        s += h;
+        nz += h != 0;
+        if (h >= 2) {
+            const double hd = (double)h;
+            acc = dd_add(acc, dd_mul_d(dd_ln_int(hd, ln2, coef), hd));
+        }
+    }
+    block_reduce(acc, s, nz, sh, ss, sz);
+    if (threadIdx.x == 0) entropy_finish(acc, s, nz, ln2, coef, out + 4 * (int64_t)blockIdx.x);
 }
 
 }  // namespace
@@ -229,6 +269,44 @@ hipError_t launch_entropy(const uint32_t *hist, int64_t bins, double *result, vo
     hipLaunchKernelGGL(k_entropy_partial, dim3(g), dim3(kBlock), 0, s, hist, bins, part);
     hipLaunchKernelGGL(k_entropy_final, dim3(1), dim3(kBlock), 0, s, (const EntPartial *)part, g,
                        result);
+    return hipGetLastError();
+}
+
+int32_t entropy_regions_count(int32_t grid_r, int32_t grid_c, const int32_t *levels,
+                              int32_t nlevels) {
+    int32_t n = 0;
+    for (int32_t i = 0; i < nlevels; ++i)
+        n += std::min(levels[i], grid_r) * std::min(levels[i], grid_c);
+    return n;
+}
+
+size_t entropy_regions_ws_bytes(int32_t nregions) {
+    return ((sizeof(Region) * (size_t)nregions + 255) & ~size_t(255));
+}
+
+hipError_t launch_entropy_regions(const uint32_t *hist, int32_t grid_r, int32_t grid_c,
+                                  const int32_t *levels, int32_t nlevels, double *result,
+                                  void *ws, hipStream_t s) {
+    // region (a, b) of level L holds the bins r with floor(r * Lr / G_r) = a,
+    // i.e. r in [ceil(a G_r / Lr), ceil((a + 1) G_r / Lr)), and likewise columns
+    std::vector<Region> regs;
+    for (int32_t i = 0; i < nlevels; ++i) {
+        const int64_t lr = std::min(levels[i], grid_r), lc = std::min(levels[i], grid_c);
+        for (int64_t a = 0; a < lr; ++a)
+            for (int64_t b = 0; b < lc; ++b)
+                regs.push_back(Region{(int32_t)((a * grid_r + lr - 1) / lr),
+                                      (int32_t)(((a + 1) * grid_r + lr - 1) / lr),
+                                      (int32_t)((b * grid_c + lc - 1) / lc),
+                                      (int32_t)(((b + 1) * grid_c + lc - 1) / lc)});
+    }
+    if (regs.empty()) return hipSuccess;
+    hipError_t e = hipMemcpyAsync(ws, regs.data(), sizeof(Region) * regs.size(),
+                                  hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return e;
+    // the staging copy must land before the host vector goes away
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_entropy_regions, dim3((unsigned)regs.size()), dim3(kBlock), 0, s, hist,
+                       grid_c, (const Region *)ws, result);
     return hipGetLastError();
 }
 

@@ -30,6 +30,7 @@ namespace mxe {
 namespace {
 
 constexpr int kBlock = 256;
+constexpr int32_t kFixedParts = 256 * 8;     // FIXED: one part per resident workgroup slot
 
 inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
@@ -338,32 +339,57 @@ __global__ __launch_bounds__(kBlock) void k_merge_fixup(int32_t ntiles, const Ca
 // kernel needs the registers of a single accumulator. Groups are L-aligned, so
 // xor shuffles below L stay inside a group.
 template <typename V, typename T>
-__device__ inline void batch_tile_l(const BatchDesc &d, int32_t r0, int32_t r1) {
-    const int L = d.lanes, KM = d.kclass, E = L / KM;
+__device__ inline void rows_runtime(const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
+                                    const V *__restrict__ val, int32_t k, const T *__restrict__ X,
+                                    int64_t ldx, T *__restrict__ Y, int64_t ldy, int L, int KM,
+                                    int32_t r0, int32_t r1) {
+    const int E = L / KM;
     const int lane = threadIdx.x % L, q = lane % KM, el = lane / KM;
-    const bool active = q < d.k;
-    const T *X = (const T *)d.X;
-    const V *val = (const V *)d.val;
+    const bool active = q < k;
     for (int32_t row = r0 + threadIdx.x / L; row < r1; row += kBlock / L) {
-        const int32_t s = ld_stream(d.rp + row), e = ld_stream(d.rp + row + 1);
+        const int32_t s = ld_stream(rp + row), e = ld_stream(rp + row + 1);
         T acc = T(0);
         int32_t p = s + el;
         for (; p + E < e; p += 2 * E) {
-            const int32_t c0 = ld_stream(d.col + p), c1 = ld_stream(d.col + p + E);
+            const int32_t c0 = ld_stream(col + p), c1 = ld_stream(col + p + E);
             const T a0 = ValLoad<V, T>::get(val + p), a1 = ValLoad<V, T>::get(val + p + E);
-            const T x0 = active ? X[(int64_t)c0 * d.ldx + q] : T(0);
-            const T x1 = active ? X[(int64_t)c1 * d.ldx + q] : T(0);
+            const T x0 = active ? X[(int64_t)c0 * ldx + q] : T(0);
+            const T x1 = active ? X[(int64_t)c1 * ldx + q] : T(0);
             acc += a0 * x0;
             acc += a1 * x1;
         }
         if (p < e) {
-            const int32_t c0 = ld_stream(d.col + p);
+            const int32_t c0 = ld_stream(col + p);
             const T a0 = ValLoad<V, T>::get(val + p);
-            acc += a0 * (active ? X[(int64_t)c0 * d.ldx + q] : T(0));
+            acc += a0 * (active ? X[(int64_t)c0 * ldx + q] : T(0));
         }
         for (int off = L / 2; off >= KM; off >>= 1) acc += __shfl_xor(acc, off);
-        if (el == 0 && active) ((T *)d.Y)[(int64_t)row * d.ldy + q] = acc;
+        if (el == 0 && active) Y[(int64_t)row * ldy + q] = acc;
     }
+}
+
+template <typename V, typename T>
+__device__ inline void batch_tile_l(const BatchDesc &d, int32_t r0, int32_t r1) {
+    rows_runtime<V, T>(d.rp, d.col, (const V *)d.val, d.k, (const T *)d.X, d.ldx, (T *)d.Y, d.ldy,
+                       d.lanes, d.kclass, r0, r1);
+}
+
+// FIXED: the equal-row split of Section 7's parallel CSR on the GPU. A fixed
+// grid of P workgroups; workgroup w owns rows [w M / P, (w + 1) M / P) and
+// nothing rebalances them, so a cluster of heavy rows makes laggards unless
+// a random row permutation has spread it (the paper's load-balance argument,
+// Section 1).
+template <typename V, typename T>
+__global__ __launch_bounds__(kBlock) void k_spmv_fixed(int32_t nrows, int32_t parts,
+                                                       const int32_t *__restrict__ rp,
+                                                       const int32_t *__restrict__ col,
+                                                       const V *__restrict__ val, int32_t k,
+                                                       const T *__restrict__ X, int64_t ldx,
+                                                       T *__restrict__ Y, int64_t ldy, int L,
+                                                       int KM) {
+    const int64_t w = blockIdx.x;
+    const int32_t r0 = (int32_t)(w * nrows / parts), r1 = (int32_t)((w + 1) * nrows / parts);
+    rows_runtime<V, T>(rp, col, val, k, X, ldx, Y, ldy, L, KM, r0, r1);
 }
 
 // Persistent grid: each workgroup takes the next tile index from a device
@@ -465,6 +491,14 @@ hipError_t spmv_k(const SpmvArgs &a, int variant, hipStream_t s) {
     if (family == MXE_VAR_MERGE) {
         if constexpr (KM <= 4) return merge_launch<V, T, KM>(a, s);
         return hipErrorInvalidValue;
+    }
+    if (family == MXE_VAR_FIXED) {
+        const int L = std::max(lanes, KM);
+        const int32_t parts = kFixedParts;
+        hipLaunchKernelGGL((k_spmv_fixed<V, T>), dim3(parts), dim3(kBlock), 0, s, a.nrows, parts,
+                           a.rp, a.col, (const V *)a.val, a.k, (const T *)a.X, a.ldx, (T *)a.Y,
+                           a.ldy, L, KM);
+        return hipGetLastError();
     }
     return hipErrorInvalidValue;
 }

@@ -24,9 +24,9 @@ F64, F32, BF16 = 0, 1, 2
 DTYPES = {"f64": F64, "f32": F32, "bf16": BF16}
 # flags
 INPUT_DEVICE = OUTPUT_DEVICE = 0x1
-ROWS, COLS = 0x1, 0x2
+ROWS, COLS, GRADIENT = 0x1, 0x2, 0x4
 SPACE_PERMUTED, SPACE_ORIGINAL = 0x0, 0x1
-VAR_GROUP, VAR_BINNED, VAR_MERGE, VAR_SLAB = 0x000, 0x100, 0x200, 0x300
+VAR_GROUP, VAR_BINNED, VAR_MERGE, VAR_SLAB, VAR_FIXED = 0x000, 0x100, 0x200, 0x300, 0x400
 
 
 def variant(family: int, lanes: int = 0) -> int:
@@ -85,6 +85,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "mxe_matrix_info": ([P, i64, P], st),
         "mxe_release": ([P, i64], st),
         "mxe_entropy": ([P, i64, i32, i32, P, P, P, P], st),
+        "mxe_entropy_levels": ([P, i64, i32, i32, P, i32, P, P, P], st),
         "mxe_spmv": ([P, i64, i32, P, i64, P, i64, u32, P], st),
         "mxe_gather_x": ([P, i64, i32, P, i64, P, i64, P], st),
         "mxe_scatter_y": ([P, i64, i32, P, i64, P, i64, P], st),
@@ -284,6 +285,24 @@ class Context:
                                      ctypes.byref(hb), ctypes.byref(hn),
                                      _np_ptr(h) if hist else None), "mxe_entropy")
         return (hb.value, hn.value, h) if hist else (hb.value, hn.value)
+
+    def entropy_levels(self, m: int, grid_rows: int, grid_cols: int, levels=(2, 4, 8),
+                       stream=None):
+        """Hierarchical 2D entropy: a list of (bits, nats) arrays, one
+        [min(L, grid_rows), min(L, grid_cols)] pair per level L."""
+        lv = np.ascontiguousarray(levels, dtype=np.int32)
+        shapes = [(min(L, grid_rows), min(L, grid_cols)) for L in levels]
+        n = sum(a * b for a, b in shapes)
+        hb = np.empty(n, np.float64)
+        hn = np.empty(n, np.float64)
+        _check(self._lib.mxe_entropy_levels(self._h, m, grid_rows, grid_cols, _np_ptr(lv), len(lv),
+                                            _stream_ptr(stream), _np_ptr(hb), _np_ptr(hn)),
+               "mxe_entropy_levels")
+        out, o = [], 0
+        for a, b in shapes:
+            out.append((hb[o:o + a * b].reshape(a, b), hn[o:o + a * b].reshape(a, b)))
+            o += a * b
+        return out
 
     # --- products -------------------------------------------------------------
     def _fp64(self, m: int) -> bool:

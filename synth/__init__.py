@@ -19,7 +19,7 @@ from dataclasses import dataclass
 import numpy as np
 
 __all__ = [
-    "CSR", "from_entries", "block_clustered", "skewed_clustered",
+    "CSR", "from_entries", "block_clustered", "skewed_clustered", "heavy_clustered",
     "config1", "config2", "config3", "config4", "config5",
     "random_csr", "vector", "uniform_fill",
 ]
@@ -133,6 +133,32 @@ def skewed_clustered(n: int, mu: float, sigma: float, cap: int, spread: float,
 
     cols = draw(np.arange(len(rows)))
     cols = _dedupe(rows, cols, n, draw)
+    vals = rng.uniform(-1.0, 1.0, size=len(rows))
+    return from_entries(n, n, rows, cols, vals)
+
+
+def heavy_clustered(n: int, base_len: int, heavy_frac: float, heavy_len: int, spread: float,
+                    seed: int) -> CSR:
+    """A stand-in for a matrix with a few very heavy rows that are clustered
+    (the paper's LP OSA 07, Section 5): every row has base_len entries except
+    one contiguous band of heavy_frac * n rows with heavy_len entries each;
+    columns are rint(i + spread * z) around the diagonal, distinct in a row.
+    No row is dense (heavy_len << n). Values U[-1, 1]."""
+    rng = np.random.default_rng(seed)
+    lens = np.full(n, base_len, dtype=np.int64)
+    start = int(rng.integers(0, max(1, n - int(heavy_frac * n))))
+    lens[start:start + int(heavy_frac * n)] = heavy_len
+    rows = np.repeat(np.arange(n, dtype=np.int64), lens)
+
+    def draw(idx):
+        out = np.rint(rows[idx] + spread * rng.standard_normal(len(idx))).astype(np.int64)
+        bad = np.nonzero((out < 0) | (out >= n))[0]
+        while len(bad):
+            out[bad] = np.rint(rows[idx[bad]] + spread * rng.standard_normal(len(bad))).astype(np.int64)
+            bad = bad[(out[bad] < 0) | (out[bad] >= n)]
+        return out
+
+    cols = _dedupe(rows, draw(np.arange(len(rows))), n, draw)
     vals = rng.uniform(-1.0, 1.0, size=len(rows))
     return from_entries(n, n, rows, cols, vals)
 

@@ -159,7 +159,8 @@ def test_entropy_rejects_bad_grid(ctx):
 
 VARIANTS = [mx.variant(mx.VAR_GROUP, lanes) for lanes in (1, 2, 4, 8, 16, 32, 64)] + \
            [mx.variant(mx.VAR_BINNED), mx.variant(mx.VAR_MERGE),
-            mx.variant(mx.VAR_SLAB, 1), mx.variant(mx.VAR_SLAB, 32)]   # 64 KiB and 2 MiB slabs
+            mx.variant(mx.VAR_SLAB, 1), mx.variant(mx.VAR_SLAB, 32),   # 64 KiB and 2 MiB slabs
+            mx.variant(mx.VAR_FIXED, 4), mx.variant(mx.VAR_FIXED, 16)]
 
 
 def _force(ctx, H, k, v):
@@ -295,5 +296,65 @@ def test_full_size_config2(ctx):
         ctx.spmv(H, xt, y)
         torch.cuda.synchronize()
         assert spmv_error(Ho, x, y.cpu().numpy(), "f64") <= 1e-13
+    ctx.release(B)
+    ctx.release(A)
+
+
+# --- hierarchical entropy, gradient formats, fixed partition ------------------------
+
+@pytest.mark.parametrize("case,grid", [("config1", (64, 64)), ("skewed", (64, 64)),
+                                       ("wide", (5, 1000)), ("ragged", (37, 23))])
+def test_entropy_levels_exact(ctx, case, grid):
+    A0 = dict(CSR_CASES)[case]()
+    A = ctx.register(A0)
+    B = ctx.permute(A, 3)
+    levels = (1, 2, 4, 8)
+    for H in (A, B):
+        rp, col, _ = ctx.export_csr(H)
+        ref_h = oracle.block_hist(A0.nrows, A0.ncols, rp, col, grid[0], grid[1])
+        got = ctx.entropy_levels(H, grid[0], grid[1], levels)
+        ref = oracle.entropy_levels(ref_h, levels)
+        for (gb, gn), (rb, rn) in zip(got, ref):
+            assert np.array_equal(gb, rb) and np.array_equal(gn, rn), case
+        assert got[0][0][0, 0] == ctx.entropy(H, grid[0], grid[1])[0]
+    ctx.release(B)
+    ctx.release(A)
+
+
+GRAD_CASES = CSR_CASES + [("one_row", lambda: synth.random_csr(1, 9, 0.5, 1)),
+                          ("two_rows", lambda: synth.random_csr(2, 2, 1.0, 2)),
+                          ("heavy", lambda: synth.heavy_clustered(30_000, 8, 0.02, 200, 2000.0, 4))]
+
+
+@pytest.mark.parametrize("name,make", GRAD_CASES)
+def test_gradient_formats_bit_exact(ctx, name, make):
+    A0 = make()
+    A = ctx.register(A0)
+    for mode in (mx.ROWS | mx.GRADIENT, mx.ROWS | mx.COLS | mx.GRADIENT, mx.COLS | mx.GRADIENT):
+        B = ctx.permute(A, 13, mode)
+        rperm, cperm = ctx.get_permutation(B)
+        er, ec, (rp, col, val) = oracle.permute_gradient(A0, 13, mode)
+        assert np.array_equal(rperm, er), (name, mode)
+        assert np.array_equal(cperm, ec), (name, mode)
+        gr, gc, gv = ctx.export_csr(B)
+        assert np.array_equal(gr, rp) and np.array_equal(gc, col) and np.array_equal(gv, val)
+        ctx.release(B)
+    ctx.release(A)
+
+
+def test_fixed_partition_variant(ctx):
+    A0 = synth.heavy_clustered(50_000, 8, 0.02, 256, 2000.0, 5)
+    x = synth.vector(A0.ncols, 2, k=3)
+    A = ctx.register(A0)
+    B = ctx.permute(A, 3, mx.ROWS)
+    rperm, cperm = ctx.get_permutation(B)
+    Bo = synth.CSR(A0.nrows, A0.ncols, *oracle.permute_csr(A0, rperm, cperm))
+    for H, Ho in ((A, A0), (B, Bo)):
+        for lanes in (1, 8, 64):
+            ctx.set_variant(H, 3, mx.variant(mx.VAR_FIXED, lanes))
+            Y = torch.full((A0.nrows, 3), float("nan"), dtype=torch.float64, device="cuda")
+            ctx.spmv(H, torch_vec(x, torch.float64), Y)
+            torch.cuda.synchronize()
+            assert spmv_error(Ho, x, Y.cpu().numpy(), "f64") <= TOL["f64"], lanes
     ctx.release(B)
     ctx.release(A)

@@ -349,3 +349,72 @@ def test_normalized_error_hand_cases():
     assert oracle.normalized_error(3, A.row_ptr, A.col, A.val, x, y, ref) == pytest.approx(5e-4)
     y = np.array([0.0, 1e-300, 2.0])    # empty row must be exactly zero
     assert oracle.normalized_error(3, A.row_ptr, A.col, A.val, x, y, ref) == float("inf")
+
+
+# --- hierarchical entropy (Section 5) ---------------------------------------------
+
+def test_entropy_levels_uniform_and_global():
+    h = np.full((64, 64), 16)
+    lv = oracle.entropy_levels(h, levels=(1, 2, 4, 8))
+    assert lv[0][0][0, 0] == oracle.entropy(h)[0] == 12.0       # one region: the global H
+    for (bits, _), expect in zip(lv[1:], (10.0, 8.0, 6.0)):     # 32x32, 16x16, 8x8 bins each
+        assert np.all(bits == expect)
+
+
+def test_entropy_levels_hand_cases():
+    h = np.array([[1, 0], [0, 3]])
+    (bits, nats), = oracle.entropy_levels(h, levels=(2,))
+    assert np.all(bits == 0.0) and np.all(nats == 0.0)          # one nonzero bin per region
+    h = np.array([[1, 1, 0, 4], [2, 2, 0, 0]])
+    (bits, _), = oracle.entropy_levels(h, levels=(2,))
+    assert bits.shape == (2, 2)
+    assert bits[0, 0] == 1.0 and bits[1, 0] == 1.0                # two equal bins
+    assert bits[0, 1] == 0.0 and bits[1, 1] == 0.0
+    (bits, _), = oracle.entropy_levels(np.ones((3, 5), np.int64), levels=(4,))
+    assert bits.shape == (3, 4)                                    # fewer regions than L rows
+
+
+# --- gradient shuffle (Sections 5 and 8) -------------------------------------------
+
+def test_gradient_permutation_structure():
+    h = np.array([1, 1, 1, 9, 9, 9, 9, 9, 2])     # steepest rise between rows 2 and 3
+    s = oracle.stream_seeds(5)[0]
+    p = oracle.gradient_permutation(h, s)
+    assert sorted(p.tolist()) == list(range(9))
+    A, B = {0, 1, 2}, {3, 4, 5, 6, 7, 8}
+    # riffle: A and B alternate while both last, then B's remainder
+    assert [int(v) in A for v in p[:6:2]] == [True] * 3
+    assert all(int(v) in B for v in p[1:6:2]) and all(int(v) in B for v in p[6:])
+    keys = oracle.splitmix64_outputs(s, 9)
+    a_order = [int(v) for v in p if int(v) in A]
+    b_order = [int(v) for v in p if int(v) in B]
+    assert a_order == sorted(A, key=lambda i: (keys[i], i))       # random order inside each part
+    assert b_order == sorted(B, key=lambda i: (keys[i], i))
+
+
+def test_gradient_permutation_edges():
+    s = oracle.stream_seeds(1)[0]
+    assert oracle.gradient_permutation([], s).tolist() == []
+    assert oracle.gradient_permutation([7], s).tolist() == [0]
+    p = oracle.gradient_permutation([5, 5, 5], s)                  # ties: first index, p = 0
+    assert p[0] == 0 and sorted(p[1:].tolist()) == [1, 2]
+    p = oracle.gradient_permutation([3, 2, 1, 0], s)              # all falling: max gradient -1 at 0
+    assert p[0] == 0
+    for n in (2, 17, 1000):
+        h = np.random.default_rng(n).integers(0, 50, size=n)
+        q = oracle.gradient_permutation(h, s)
+        assert np.array_equal(np.sort(q), np.arange(n))
+
+
+def test_permute_gradient_modes():
+    A = synth.random_csr(40, 30, 0.2, 3)
+    rperm, cperm, (rp, col, val) = oracle.permute_gradient(A, 7, oracle.ROWS | oracle.GRADIENT)
+    assert np.array_equal(cperm, np.arange(30))
+    s_r, s_c = oracle.stream_seeds(7)
+    assert np.array_equal(rperm, oracle.gradient_permutation(A.row_lengths(), s_r))
+    rperm, cperm, _ = oracle.permute_gradient(A, 7, oracle.ROWS | oracle.COLS | oracle.GRADIENT)
+    assert np.array_equal(cperm, oracle.gradient_permutation(np.bincount(A.col, minlength=30), s_c))
+    S = _scipy(A)[rperm][:, cperm].tocsr()
+    S.sort_indices()
+    _, _, (rp, col, val) = oracle.permute_gradient(A, 7, oracle.ROWS | oracle.COLS | oracle.GRADIENT)
+    assert np.array_equal(rp, S.indptr) and np.array_equal(col, S.indices)

@@ -61,3 +61,12 @@ def test_uniform_fill_is_uniform():
     h = np.zeros((64, 64), int)
     np.add.at(h, (rows // 64, U.col // 64), 1)
     assert np.all(h == 16)
+
+
+def test_heavy_clustered_structure():
+    A = synth.heavy_clustered(20_000, 8, 0.02, 256, 2000.0, 3)
+    _canonical(A)
+    L = A.row_lengths()
+    heavy = np.nonzero(L == 256)[0]
+    assert len(heavy) == 400 and np.all(np.diff(heavy) == 1)      # one contiguous band
+    assert np.all(L[L != 256] == 8)
