@@ -7,6 +7,11 @@
   batch       64 matrices (rows log-uniform in [10k, 500k], 8-32 nnz per row,
               block-clustered), k in {1, 2, 4, 8, 16}, FP32; one persistent
               launch replayed from a HIP graph.
+  heavy       2,000,000-row CSR, 8 nnz per row except one contiguous band of
+              1% of the rows with 512 each (heavy clustered rows): SpMV with
+              the fixed equal-row partition (no counting) and with the tuned
+              count-aware variant on the original, R, RC and gradient (G-R,
+              G-RC) orderings, plus the hierarchical 2D entropy of each.
   serving     32 resident permuted matrices of 50k-2M rows (FP32), requests of
               1-8 right-hand sides on a random matrix; closed-loop saturation
               rate, then open-loop Poisson arrivals at 0.5 and 0.8 of it:
@@ -73,6 +78,52 @@ def skewed(ctx, log, n=4_000_000, reps=50):
         log(f"skewed {st}: {r}")
         ctx.release(B)
         ctx.release(A)
+    return out
+
+
+def heavy(ctx, log, n=2_000_000, reps=50):
+    import torch
+    from paper_2308_00106_amd import mxe as mx
+    stream = torch.cuda.current_stream()
+    t = time.perf_counter()
+    A0 = synth.heavy_clustered(n, 8, 0.01, 512, 2000.0, 7)
+    x = synth.vector(A0.ncols, 2)
+    log(f"heavy: generated n={n} nnz={A0.nnz} in {time.perf_counter() - t:.1f}s")
+    yref = oracle.spmv(A0, x)
+    nb = _bytes(A0, 8, 8, 1)
+    out = {"n": n, "nnz": A0.nnz, "heavy_rows": int((A0.row_lengths() == 512).sum())}
+    A = ctx.register(A0)
+    xt = torch.from_numpy(x).to(device="cuda")
+    y = torch.empty(A0.nrows, dtype=torch.float64, device="cuda")
+    forms = {"original": None, "R": mx.ROWS, "RC": mx.ROWS | mx.COLS,
+             "G-R": mx.ROWS | mx.GRADIENT, "G-RC": mx.ROWS | mx.COLS | mx.GRADIENT}
+    for name, mode in forms.items():
+        H = A if mode is None else ctx.permute(A, 3, mode, stream=stream)
+        r = {}
+        for lanes in (8, 32):
+            ctx.set_variant(H, 1, mx.variant(mx.VAR_FIXED, lanes))
+            us = _time(ctx, H, xt, y, reps, stream)
+            r[f"fixed_l{lanes}_us"] = round(us, 2)
+        v = ctx.tune(H, 1, stream=stream)
+        us = _time(ctx, H, xt, y, reps, stream)
+        r["tuned_us"] = round(us, 2)
+        r["tuned_variant"] = hex(v)
+        r["tuned_gbs"] = round(nb / (us * 1e-6) / 1e9, 1)
+        ctx.spmv(H, xt, y, flags=mx.SPACE_ORIGINAL, stream=stream)
+        torch.cuda.synchronize()
+        r["max_normalized_error_vs_fp64_oracle"] = oracle.normalized_error(
+            A0.nrows, A0.row_ptr, A0.col, A0.val, x, y.cpu().numpy(), yref)
+        r["entropy_bits_64"] = ctx.entropy(H, 64, 64)[0]
+        t0 = time.perf_counter()
+        lv = ctx.entropy_levels(H, 64, 64, (2, 4, 8), stream=stream)
+        r["levels_ms"] = round((time.perf_counter() - t0) * 1e3, 3)
+        r["levels_bits"] = {L: np.round(b, 3).tolist() for L, (b, _) in zip((2, 4), lv[:2])}
+        r["levels8_bits_min_max"] = [round(float(lv[2][0].min()), 3), round(float(lv[2][0].max()), 3)]
+        out[name] = r
+        log(f"heavy {name}: {r}")
+        if mode is not None:
+            ctx.release(H)
+    ctx.release(A)
     return out
 
 
@@ -217,4 +268,5 @@ def serving(ctx_unused, log, pool=32, warm=1000, n_req=20000):
 
 
 def run_all(ctx, log):
-    return {"skewed": skewed(ctx, log), "batch": batch(ctx, log), "serving": serving(ctx, log)}
+    return {"skewed": skewed(ctx, log), "heavy": heavy(ctx, log), "batch": batch(ctx, log),
+            "serving": serving(ctx, log)}

@@ -11,7 +11,7 @@
 // into S slabs whose x slice fits comfortably in one L2; rows are cut into
 // workgroup blocks of R rows, each split into 16 wavefront sub-blocks. Entries
 // are stored grouped by (block, sub-block, slab), rows ascending inside a
-// group, each as one 32-bit word (row in sub-block << cbits | column in slab)
+// group, each as one 32-bit word (row in sub-block << cbits | global column)
 // plus its value. The product keeps each block's partial y in LDS and walks
 // the slabs in a rotation that starts at a slab tied to the workgroup's XCD
 // (workgroups are dealt to the 8 XCDs round-robin), so at any moment an XCD's
