@@ -28,6 +28,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+FP64_TOL = 1e-13               # max_i |y - y_ref| / (|A||x|)_i against the FP64 oracle
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "spmv_permuted_config2_traffic.txt")
 
 
@@ -264,6 +265,7 @@ def main():
         "permuted_frac_of_measured_read_ceiling": round(perm_gbs / ceiling["read_gbs"], 4),
         "entropy_bits": {"original": h_a[0], "permuted": h_b[0], "max": 20.0},
         "max_normalized_error": err,
+        "parity_ok": bool(err <= FP64_TOL),
         "paper_context": "paper reports up to ~15% from randomization on AMD GPU/CPU systems "
                          "(Vega 20 / Fiji / Ellesmere, rocSPARSE FP64); context only",
     }
@@ -275,6 +277,9 @@ def main():
         out["cpu_baseline"] = cpu_baseline(A0, x, seed, reps, grid)
     ctx.close()
     print(json.dumps(out), flush=True)
+    if not out["parity_ok"]:
+        print(f"[bench] parity FAILED: max normalized error {err:.3e} > {FP64_TOL}", file=sys.stderr)
+        sys.exit(1)
 
 
 if __name__ == "__main__":
