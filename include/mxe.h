@@ -211,6 +211,12 @@ mxe_status mxe_scatter_y(mxe_ctx *ctx, mxe_mat b, int32_t k, const void *Yp, int
  * fixed grid of 2048 workgroups each owning an equal contiguous share of rows,
  * nothing rebalanced (the case where the paper sees randomization help). */
 #define MXE_VAR_FIXED   0x400
+/* MXE_VAR_COO (lanes ignored, 0): Section 2's coordinate format. The first
+ * use builds a row index per stored entry (4 bytes per nonzero, counted in
+ * the HBM budget, kept until the matrix is released); every 256-entry tile
+ * is reduced by row and the rows cut by a tile edge are joined by a second
+ * pass. Never chosen by mxe_tune; force it with mxe_set_variant. */
+#define MXE_VAR_COO     0x500
 #define MXE_VARIANT(family, lanes) ((family) | (lanes))
 
 /* Times the candidate variants for (m, k) on the device and caches the

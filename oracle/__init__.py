@@ -15,6 +15,10 @@ Parity status per function (what pins it is in tests/test_oracle.py):
   block_hist                        pinned (dense brute force, remap invariance)
   entropy                           pinned (closed forms, uniform fill, scipy)
   spmm / spmv                       pinned (dense brute force, scipy)
+  coo_rows, coo_spmm                pinned (dense brute force, scipy COO, shuffled entry order)
+  entropy_levels                    pinned (uniform fill per level, hand cases, L = 1 is the global H)
+  gradient_permutation, permute_gradient
+                                    pinned (hand-built step profile, ties, edges, scipy slicing)
   round_f32, round_bf16             pinned (IEEE halfway cases, torch for FP32-exact inputs)
   normalized_error                  pinned (hand cases)
 """
@@ -64,6 +68,7 @@ def _c():
         lib.orc_block_hist.argtypes = [i32, i32, P, P, i32, i32, P]
         lib.orc_spmm.argtypes = [i32, P, P, P, i32, P, i64, P, i64]
         lib.orc_spmm_parallel.argtypes = [i32, P, P, P, i32, P, i64, P, i64]
+        lib.orc_coo_spmm.argtypes = [i32, i64, P, P, P, i32, P, i64, P, i64]
         lib.orc_omp_max_threads.restype = ctypes.c_int
         lib.orc_round_f32.argtypes = [i64, P, P]
         lib.orc_round_bf16.argtypes = [i64, P, P]
@@ -258,6 +263,25 @@ def spmm(nrows: int, row_ptr, col, val, X: np.ndarray) -> np.ndarray:
 
 def spmv(A, x):
     return spmm(A.nrows, A.row_ptr, A.col, A.val, x)
+
+
+def coo_rows(row_ptr) -> np.ndarray:
+    """COO row index of every stored entry of a CSR matrix (Section 2: entry
+    l of row i has ROW[l] = i), i.e. i repeated row_ptr[i+1] - row_ptr[i] times."""
+    rp = np.asarray(row_ptr, dtype=np.int64)
+    return np.repeat(np.arange(len(rp) - 1, dtype=np.int32), np.diff(rp))
+
+
+def coo_spmm(nrows: int, row, col, val, X: np.ndarray) -> np.ndarray:
+    """Y = A X for A in COO form (any entry order, no duplicates required):
+    Y = 0, then every entry in storage order adds val * X[col] to Y[row]."""
+    X = np.asarray(X, dtype=np.float64)
+    k = 1 if X.ndim == 1 else X.shape[1]
+    X2 = np.ascontiguousarray(X.reshape(len(X), k))
+    Y = np.empty((nrows, k), dtype=np.float64)
+    r, c, v = _c_i32(row), _c_i32(col), _c_f64(val)
+    _c().orc_coo_spmm(nrows, len(r), _p(r), _p(c), _p(v), k, _p(X2), k, _p(Y), k)
+    return Y[:, 0].copy() if X.ndim == 1 else Y
 
 
 def spmm_parallel(nrows: int, row_ptr, col, val, X: np.ndarray, Y: np.ndarray) -> None:

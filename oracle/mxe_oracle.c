@@ -177,6 +177,22 @@ void orc_spmm(int32_t nrows, const int32_t *rp, const int32_t *col, const double
     }
 }
 
+/* COO SpMV / SpMM (Section 2's coordinate format): Y starts at zero and   */
+/* every stored entry l, in storage order, adds V[l] * x[COL[l]] to row     */
+/* ROW[l]. On entries sorted by row this adds each row's terms in the same  */
+/* order as orc_spmm.                                                       */
+void orc_coo_spmm(int32_t nrows, int64_t nnz, const int32_t *row, const int32_t *col,
+                  const double *val, int32_t k, const double *x, int64_t ldx, double *y,
+                  int64_t ldy)
+{
+    for (int32_t i = 0; i < nrows; ++i)
+        for (int32_t c = 0; c < k; ++c)
+            y[(int64_t)i * ldy + c] = 0.0;
+    for (int64_t e = 0; e < nnz; ++e)
+        for (int32_t c = 0; c < k; ++c)
+            y[(int64_t)row[e] * ldy + c] += val[e] * x[(int64_t)col[e] * ldx + c];
+}
+
 /* Same arithmetic, rows split evenly over OpenMP threads with a static
  * schedule: the equal-row split of Section 7's parallel CSR experiment. It is
  * timed as the CPU baseline; its results equal orc_spmm's bit for bit. */

@@ -162,6 +162,22 @@ static mxe_status ensure_merge_ws(Matrix &A, hipStream_t s) {
     return MXE_OK;
 }
 
+// COO row index and carry workspace (built once per matrix)
+static mxe_status ensure_coo(mxe_ctx *ctx, Matrix &A, hipStream_t s) {
+    if (A.coo_row) return MXE_OK;
+    const uint64_t bytes = 4ull * (uint64_t)A.nnz + coo_ws_bytes(A.nnz);
+    mxe_status st;
+    if ((st = reserve(ctx, bytes))) return st;
+    A.bytes += bytes;
+    void *r, *w;
+    if ((st = dev_alloc(A, &r, 4 * (size_t)A.nnz, s))) return st;
+    if ((st = dev_alloc(A, &w, coo_ws_bytes(A.nnz), s))) return st;
+    MXE_HIP(launch_coo_rows(A.nrows, A.rp, (int32_t *)r, s));
+    A.coo_row = (int32_t *)r;
+    A.coo_ws = w;
+    return MXE_OK;
+}
+
 static SpmvArgs make_args(Matrix &A, int32_t k, const void *X, int64_t ldx, void *Y, int64_t ldy) {
     SpmvArgs a{};
     a.nrows = A.nrows;
@@ -179,6 +195,8 @@ static SpmvArgs make_args(Matrix &A, int32_t k, const void *X, int64_t ldx, void
     a.bin_list = A.bin_list;
     a.bin_off_host = A.bin_off;
     a.merge_ws = A.merge_ws;
+    a.coo_row = A.coo_row;
+    a.coo_ws = A.coo_ws;
     return a;
 }
 
@@ -233,6 +251,7 @@ static mxe_status prepare_args(mxe_ctx *ctx, Matrix &A, int variant, int32_t k, 
     mxe_status st;
     if (family == MXE_VAR_BINNED && (st = ensure_bins(ctx, A, s))) return st;
     if (family == MXE_VAR_MERGE && (st = ensure_merge_ws(A, s))) return st;
+    if (family == MXE_VAR_COO && (st = ensure_coo(ctx, A, s))) return st;
     *a = make_args(A, k, X, ldx, Y, ldy);
     if (family == MXE_VAR_SLAB) {
         const Matrix::Slab *sl;
@@ -761,7 +780,7 @@ mxe_status mxe_entropy_levels(mxe_ctx *ctx, mxe_mat m, int32_t grid_rows, int32_
     Scratch hdev, ws, res;
     mxe_status st;
     if ((st = hdev.alloc(4 * (size_t)bins, s))) return st;
-    if ((st = ws.alloc(entropy_regions_ws_bytes(nreg), s))) return st;
+    if ((st = ws.alloc(entropy_regions_ws_bytes(grid_rows, grid_cols, levels, nlevels), s))) return st;
     if ((st = res.alloc(4 * sizeof(double) * (size_t)nreg, s))) return st;
     MXE_HIP(launch_block_hist(A->nrows, A->ncols, A->nnz, A->rp, A->col, grid_rows, grid_cols,
                               (uint32_t *)hdev.p, s));
@@ -870,7 +889,7 @@ mxe_status mxe_set_variant(mxe_ctx *ctx, mxe_mat m, int32_t k, int32_t variant) 
     if ((family == MXE_VAR_GROUP || family == MXE_VAR_FIXED) && !pow2)
         return fail(MXE_ERR_INVALID_ARG, "lanes must be 1..64, a power of two");
     if (family != MXE_VAR_GROUP && family != MXE_VAR_BINNED && family != MXE_VAR_MERGE &&
-        family != MXE_VAR_SLAB && family != MXE_VAR_FIXED)
+        family != MXE_VAR_SLAB && family != MXE_VAR_FIXED && family != MXE_VAR_COO)
         return fail(MXE_ERR_INVALID_ARG, "unknown variant family");
     if (family == MXE_VAR_SLAB) {
         SlabGeom sg;

@@ -89,7 +89,8 @@ hipError_t launch_entropy(const uint32_t *hist, int64_t bins, double *result, vo
 // regions row-major. Synchronizes s (the region table is staged from the host).
 int32_t entropy_regions_count(int32_t grid_r, int32_t grid_c, const int32_t *levels,
                               int32_t nlevels);
-size_t entropy_regions_ws_bytes(int32_t nregions);
+size_t entropy_regions_ws_bytes(int32_t grid_r, int32_t grid_c, const int32_t *levels,
+                                int32_t nlevels);
 hipError_t launch_entropy_regions(const uint32_t *hist, int32_t grid_r, int32_t grid_c,
                                   const int32_t *levels, int32_t nlevels, double *result,
                                   void *ws, hipStream_t s);
@@ -137,9 +138,14 @@ struct SpmvArgs {
     const int32_t *slab_off;
     const uint32_t *slab_idx;
     const void *slab_val;
+    // COO variant: row index per entry and its carry workspace (coo_ws_bytes)
+    const int32_t *coo_row;
+    void *coo_ws;
 };
 
 size_t merge_ws_bytes(int32_t nrows, int64_t nnz);
+size_t coo_ws_bytes(int64_t nnz);                 // enough for k <= 16
+hipError_t launch_coo_rows(int32_t nrows, const int32_t *rp, int32_t *row, hipStream_t s);
 // variant: MXE_VARIANT(family, lanes) as in mxe.h
 hipError_t launch_spmv(const SpmvArgs &a, int variant, hipStream_t s);
 

@@ -210,24 +210,26 @@ __global__ __launch_bounds__(kBlock) void k_entropy_final(const EntPartial *part
     if (threadIdx.x == 0) entropy_finish(acc, s, nz, ln2, coef, result);
 }
 
-// Hierarchical 2D entropy (Section 5): one workgroup per region of one
-// level; region r covers bins [r0, r1) x [c0, c1) of the grid.
+// Hierarchical 2D entropy (Section 5). Region r covers bins [r0, r1) x
+// [c0, c1) of the grid; `parts` workgroups share each region, workgroup p
+// taking cells p*kBlock + t, p*kBlock + t + parts*kBlock, ... of it, and one
+// workgroup per region then combines the parts in index order.
 struct Region { int32_t r0, r1, c0, c1; };
 
-__global__ __launch_bounds__(kBlock) void k_entropy_regions(const uint32_t *__restrict__ hist,
-                                                            int32_t grid_c,
-                                                            const Region *__restrict__ regions,
-                                                            double *__restrict__ out) {
+__global__ __launch_bounds__(kBlock) void k_entropy_regions_partial(
+    const uint32_t *__restrict__ hist, int32_t grid_c, const Region *__restrict__ regions,
+    int32_t parts, EntPartial *__restrict__ part) {
     __shared__ dd coef[kLnTerms];
     __shared__ dd ln2;
     __shared__ dd sh[kBlock];
     __shared__ unsigned long long ss[kBlock], sz[kBlock];
     setup_log_tables(coef, &ln2);
-    const Region rg = regions[blockIdx.x];
+    const int64_t region = blockIdx.x / parts, p = blockIdx.x % parts;
+    const Region rg = regions[region];
     const int64_t w = rg.c1 - rg.c0, cells = (int64_t)(rg.r1 - rg.r0) * w;
     dd acc{0.0, 0.0};
     unsigned long long s = 0, nz = 0;
-    for (int64_t i = threadIdx.x; i < cells; i += kBlock) {
+    for (int64_t i = p * kBlock + threadIdx.x; i < cells; i += (int64_t)parts * kBlock) {
         const uint32_t h = hist[(int64_t)(rg.r0 + i / w) * grid_c + rg.c0 + i % w];
         s += h;
         nz += h != 0;
@@ -237,7 +239,42 @@ __global__ __launch_bounds__(kBlock) void k_entropy_regions(const uint32_t *__re
         }
     }
     block_reduce(acc, s, nz, sh, ss, sz);
+    if (threadIdx.x == 0) part[blockIdx.x] = EntPartial{acc.hi, acc.lo, s, nz};
+}
+
+__global__ __launch_bounds__(kBlock) void k_entropy_regions_final(const EntPartial *__restrict__ part,
+                                                                  int32_t parts,
+                                                                  double *__restrict__ out) {
+    __shared__ dd coef[kLnTerms];
+    __shared__ dd ln2;
+    __shared__ dd sh[kBlock];
+    __shared__ unsigned long long ss[kBlock], sz[kBlock];
+    setup_log_tables(coef, &ln2);
+    const EntPartial *pr = part + (int64_t)blockIdx.x * parts;
+    dd acc{0.0, 0.0};
+    unsigned long long s = 0, nz = 0;
+    for (int i = threadIdx.x; i < parts; i += kBlock) {
+        acc = dd_add(acc, dd{pr[i].hi, pr[i].lo});
+        s += pr[i].s;
+        nz += pr[i].nz;
+    }
+    block_reduce(acc, s, nz, sh, ss, sz);
     if (threadIdx.x == 0) entropy_finish(acc, s, nz, ln2, coef, out + 4 * (int64_t)blockIdx.x);
+}
+
+// Workgroups per region: enough that the largest region's cells are spread
+// at ~16 per thread, at most 64, and about 16K workgroups in total.
+int32_t region_parts(int32_t grid_r, int32_t grid_c, const int32_t *levels, int32_t nlevels,
+                     int32_t nregions) {
+    int64_t max_cells = 0;
+    for (int32_t i = 0; i < nlevels; ++i) {
+        const int64_t lr = std::min(levels[i], grid_r), lc = std::min(levels[i], grid_c);
+        max_cells = std::max(max_cells, cdiv(grid_r, lr) * cdiv(grid_c, lc));
+    }
+    int64_t p = cdiv(max_cells, 16 * (int64_t)kBlock);
+    p = std::min<int64_t>(p, 64);
+    p = std::min<int64_t>(p, std::max<int64_t>(1, 16384 / std::max(nregions, 1)));
+    return (int32_t)std::max<int64_t>(p, 1);
 }
 
 }  // namespace
@@ -280,8 +317,12 @@ int32_t entropy_regions_count(int32_t grid_r, int32_t grid_c, const int32_t *lev
     return n;
 }
 
-size_t entropy_regions_ws_bytes(int32_t nregions) {
-    return ((sizeof(Region) * (size_t)nregions + 255) & ~size_t(255));
+size_t entropy_regions_ws_bytes(int32_t grid_r, int32_t grid_c, const int32_t *levels,
+                                int32_t nlevels) {
+    const int32_t n = entropy_regions_count(grid_r, grid_c, levels, nlevels);
+    const int64_t parts = region_parts(grid_r, grid_c, levels, nlevels, n);
+    return ((sizeof(Region) * (size_t)n + 255) & ~size_t(255)) +
+           sizeof(EntPartial) * (size_t)n * (size_t)parts;
 }
 
 hipError_t launch_entropy_regions(const uint32_t *hist, int32_t grid_r, int32_t grid_c,
@@ -300,13 +341,19 @@ hipError_t launch_entropy_regions(const uint32_t *hist, int32_t grid_r, int32_t 
                                       (int32_t)(((b + 1) * grid_c + lc - 1) / lc)});
     }
     if (regs.empty()) return hipSuccess;
-    hipError_t e = hipMemcpyAsync(ws, regs.data(), sizeof(Region) * regs.size(),
+    const int32_t n = (int32_t)regs.size();
+    const int32_t parts = region_parts(grid_r, grid_c, levels, nlevels, n);
+    Region *dregs = (Region *)ws;
+    EntPartial *part = (EntPartial *)((char *)ws + ((sizeof(Region) * (size_t)n + 255) & ~size_t(255)));
+    hipError_t e = hipMemcpyAsync(dregs, regs.data(), sizeof(Region) * regs.size(),
                                   hipMemcpyHostToDevice, s);
     if (e != hipSuccess) return e;
     // the staging copy must land before the host vector goes away
     if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_entropy_regions, dim3((unsigned)regs.size()), dim3(kBlock), 0, s, hist,
-                       grid_c, (const Region *)ws, result);
+    hipLaunchKernelGGL(k_entropy_regions_partial, dim3((unsigned)((int64_t)n * parts)), dim3(kBlock),
+                       0, s, hist, grid_c, (const Region *)dregs, parts, part);
+    hipLaunchKernelGGL(k_entropy_regions_final, dim3((unsigned)n), dim3(kBlock), 0, s,
+                       (const EntPartial *)part, parts, result);
     return hipGetLastError();
 }
 

@@ -49,7 +49,8 @@ __device__ inline int32_t slab_of(int32_t col, int32_t width, double inv_w) {
     return q;
 }
 
-// Pass 1: entries per (block, sub-block, slab).
+// Pass 1: entries per (block, sub-block, slab). Lanes take consecutive
+// entries of the wavefront's sub-block (coalesced column loads).
 __global__ __launch_bounds__(kSlabBlock) void k_slab_count(SlabGeom g, const int32_t *__restrict__ rp,
                                                            const int32_t *__restrict__ col,
                                                            int32_t *__restrict__ cnt) {
@@ -60,17 +61,22 @@ __global__ __launch_bounds__(kSlabBlock) void k_slab_count(SlabGeom g, const int
     const int64_t r0 = (int64_t)blockIdx.x * g.rows_per_block + (int64_t)wave * g.rows_per_sub;
     const int64_t r1 = std::min<int64_t>(std::min<int64_t>(r0 + g.rows_per_sub,
                                          (int64_t)(blockIdx.x + 1) * g.rows_per_block), g.nrows);
-    const double inv_w = 1.0 / g.width;
-    for (int64_t r = r0 + lane; r < r1; r += kWave)
-        for (int32_t e = rp[r]; e < rp[r + 1]; ++e)
+    if (r0 < r1) {
+        const double inv_w = 1.0 / g.width;
+        const int32_t e1 = rp[r1];
+        for (int32_t e = rp[r0] + lane; e < e1; e += kWave)
             atomicAdd(&c[wave][slab_of(col[e], g.width, inv_w)], 1);
+    }
     __syncthreads();
     int32_t *out = cnt + ((int64_t)blockIdx.x * kSubBlocks + wave) * g.slabs;
     for (int s = lane; s < g.slabs; s += kWave) out[s] = c[wave][s];
 }
 
-// Pass 2: place every entry. Lanes take consecutive rows; for each slab the
-// wavefront scans the per-row counts so rows stay in order inside a group.
+// Pass 2: place every entry. A wavefront walks its sub-block's entries in
+// CSR order, 64 at a time, and splits each chunk by slab stably (lanes with
+// the same slab found with one ballot per slab-index bit), so entries keep
+// CSR order, and hence ascending rows, inside every group. Each entry's row
+// comes from a binary search of the sub-block's row_ptr slice kept in LDS.
 template <typename V>
 __global__ __launch_bounds__(kSlabBlock) void k_slab_fill(SlabGeom g, const int32_t *__restrict__ rp,
                                                           const int32_t *__restrict__ col,
@@ -78,44 +84,55 @@ __global__ __launch_bounds__(kSlabBlock) void k_slab_fill(SlabGeom g, const int3
                                                           const int32_t *__restrict__ off,
                                                           uint32_t *__restrict__ idx_out,
                                                           V *__restrict__ val_out) {
+    extern __shared__ int32_t rps[];                    // kSubBlocks x (rows_per_sub + 1)
     __shared__ int32_t base[kSubBlocks][kSlabMax];
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     const int32_t *o = off + ((int64_t)blockIdx.x * kSubBlocks + wave) * g.slabs;
     for (int s = lane; s < g.slabs; s += kWave) base[wave][s] = o[s];
-    __syncthreads();
     const int64_t r0 = (int64_t)blockIdx.x * g.rows_per_block + (int64_t)wave * g.rows_per_sub;
     const int64_t r1 = std::min<int64_t>(std::min<int64_t>(r0 + g.rows_per_sub,
                                          (int64_t)(blockIdx.x + 1) * g.rows_per_block), g.nrows);
-    for (int64_t c0 = r0; c0 < r1; c0 += kWave) {          // uniform per wavefront
-        const int64_t r = c0 + lane;
-        int32_t p = 0, end = 0;
-        if (r < r1) {
-            p = rp[r];
-            end = rp[r + 1];
+    const int32_t nr = r0 < r1 ? (int32_t)(r1 - r0) : 0;
+    int32_t *wrp = rps + wave * (g.rows_per_sub + 1);
+    for (int32_t i = lane; i <= nr; i += kWave) wrp[i] = rp[r0 + i];
+    __syncthreads();
+    if (nr == 0) return;
+    const double inv_w = 1.0 / g.width;
+    const int32_t e0 = wrp[0], e1 = wrp[nr];
+    const uint64_t below = (uint64_t(1) << lane) - 1;
+    for (int32_t c0 = e0; c0 < e1; c0 += kWave) {           // uniform per wavefront
+        const int32_t e = c0 + lane;
+        const bool valid = e < e1;
+        int32_t sl = 0, rloc = 0, cv = 0;
+        V v{};
+        if (valid) {
+            cv = col[e];
+            v = val[e];
+            sl = slab_of(cv, g.width, inv_w);
+            int32_t lo = 0, hi = nr - 1;                    // last row with wrp[row] <= e
+            while (lo < hi) {
+                const int32_t mid = (lo + hi + 1) >> 1;
+                if (wrp[mid] <= e) lo = mid;
+                else hi = mid - 1;
+            }
+            rloc = lo;
         }
-        const uint32_t rloc = (uint32_t)(r - r0);
-        for (int s = 0; s < g.slabs; ++s) {
-            const int32_t lim = (int32_t)std::min<int64_t>((int64_t)(s + 1) * g.width, g.ncols);
-            int32_t cnt = 0;
-            while (p + cnt < end && col[p + cnt] < lim) ++cnt;
-            int32_t inc = cnt;                                 // inclusive scan over lanes
+        uint64_t same = __ballot(valid);
 #pragma unroll
-            for (int d = 1; d < kWave; d <<= 1) {
-                int32_t t = __shfl_up(inc, d);
-                if (lane >= d) inc += t;
-            }
-            const int32_t total = __shfl(inc, kWave - 1);
-            const int32_t pos = base[wave][s] + inc - cnt;
-            for (int32_t i = 0; i < cnt; ++i) {
-                idx_out[pos + i] = (rloc << g.cbits) | (uint32_t)col[p + i];
-                val_out[pos + i] = val[p + i];
-            }
-            p += cnt;
-            __builtin_amdgcn_wave_barrier();
-            if (lane == 0) base[wave][s] += total;
-            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-            __builtin_amdgcn_wave_barrier();
+        for (int b = 0; b < 6; ++b) {
+            const uint64_t m = __ballot(valid && ((sl >> b) & 1));
+            same &= ((sl >> b) & 1) ? m : ~m;
         }
+        if (valid) {
+            const int32_t pos = base[wave][sl] + __popcll(same & below);
+            idx_out[pos] = ((uint32_t)rloc << g.cbits) | (uint32_t)cv;
+            val_out[pos] = v;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        if (valid && (same & below) == 0) base[wave][sl] += __popcll(same);
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
     }
 }
 
@@ -306,17 +323,18 @@ hipError_t launch_slab_build(const SlabGeom &g, const int32_t *rp, const int32_t
     hipLaunchKernelGGL(k_slab_count, dim3(g.blocks), dim3(kSlabBlock), 0, s, g, rp, col, off);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if ((e = launch_exclusive_scan(off, off, n, ws, s)) != hipSuccess) return e;
+    const size_t rps_lds = sizeof(int32_t) * kSubBlocks * ((size_t)g.rows_per_sub + 1);
     switch (val_bytes) {
     case 8:
-        hipLaunchKernelGGL(k_slab_fill<uint64_t>, dim3(g.blocks), dim3(kSlabBlock), 0, s, g, rp, col,
+        hipLaunchKernelGGL(k_slab_fill<uint64_t>, dim3(g.blocks), dim3(kSlabBlock), rps_lds, s, g, rp, col,
                            (const uint64_t *)val, (const int32_t *)off, idx_out, (uint64_t *)val_out);
         break;
     case 4:
-        hipLaunchKernelGGL(k_slab_fill<uint32_t>, dim3(g.blocks), dim3(kSlabBlock), 0, s, g, rp, col,
+        hipLaunchKernelGGL(k_slab_fill<uint32_t>, dim3(g.blocks), dim3(kSlabBlock), rps_lds, s, g, rp, col,
                            (const uint32_t *)val, (const int32_t *)off, idx_out, (uint32_t *)val_out);
         break;
     case 2:
-        hipLaunchKernelGGL(k_slab_fill<uint16_t>, dim3(g.blocks), dim3(kSlabBlock), 0, s, g, rp, col,
+        hipLaunchKernelGGL(k_slab_fill<uint16_t>, dim3(g.blocks), dim3(kSlabBlock), rps_lds, s, g, rp, col,
                            (const uint16_t *)val, (const int32_t *)off, idx_out, (uint16_t *)val_out);
         break;
     default:

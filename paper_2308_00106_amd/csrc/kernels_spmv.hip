@@ -18,6 +18,12 @@
 //          slices (Merrill and Garland, SC'16): every workgroup gets the same
 //          work whatever the row lengths; row sums that cross a slice are
 //          carried out and added by a fix-up pass in slice order.
+//   FIXED  the rows split into 2048 equal contiguous parts, one workgroup
+//          each, no counting (Section 7's equal-row parallel CSR).
+//   COO    the coordinate form (Section 2): every stored entry carries its
+//          row index; wavefronts take equal 256-entry tiles, reduce them by
+//          row with a segmented scan, write whole rows directly and hand the
+//          rows cut by a tile edge to a fix-up pass in tile order.
 // Every variant sums each row in a fixed order, so results are deterministic.
 #include "device_common.h"
 #include "internal.h"
@@ -392,6 +398,160 @@ __global__ __launch_bounds__(kBlock) void k_spmv_fixed(int32_t nrows, int32_t pa
     rows_runtime<V, T>(rp, col, val, k, X, ldx, Y, ldy, L, KM, r0, r1);
 }
 
+// ---- COO -------------------------------------------------------------------------
+
+constexpr int kCooTile = 256;                 // entries per wavefront tile
+
+__global__ __launch_bounds__(kBlock) void k_coo_rows(int32_t nrows, const int32_t *__restrict__ rp,
+                                                     int32_t *__restrict__ row) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nrows;
+         i += (int64_t)gridDim.x * blockDim.x)
+        for (int32_t e = rp[i]; e < rp[i + 1]; ++e) row[e] = (int32_t)i;
+}
+
+template <typename T, int KM>
+__global__ __launch_bounds__(kBlock) void k_zero_rows(int32_t nrows, int32_t k, T *__restrict__ Y,
+                                                      int64_t ldy) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < (int64_t)nrows * k;
+         i += (int64_t)gridDim.x * blockDim.x)
+        Y[(i / k) * ldy + i % k] = T(0);
+}
+
+// Tile t = entries [e0, e1). Its first row is a "head" carried out when it
+// began in an earlier tile; its last row is a "tail" carried out when it goes
+// on into the next tile (and is not that head). Every other row lies wholly
+// in the tile and is written here, together with the empty rows that follow
+// it. crow[2t], crow[2t+1] = head / tail row or -1; cval holds their partial
+// sums (KM values each).
+template <typename V, typename T, int KM>
+__global__ __launch_bounds__(kBlock) void k_spmv_coo(int32_t nrows, int64_t nnz,
+                                                     const int32_t *__restrict__ row,
+                                                     const int32_t *__restrict__ col,
+                                                     const V *__restrict__ val, int32_t k,
+                                                     const T *__restrict__ X, int64_t ldx,
+                                                     T *__restrict__ Y, int64_t ldy,
+                                                     int32_t *__restrict__ crow,
+                                                     T *__restrict__ cval) {
+    const int lane = threadIdx.x % kWave;
+    const int64_t t = (int64_t)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
+    const int64_t e0 = t * kCooTile;
+    if (e0 >= nnz) return;                                     // uniform per wavefront
+    const int64_t e1 = e0 + kCooTile < nnz ? e0 + kCooTile : nnz;
+    const int32_t head_row = row[e0], last_row = row[e1 - 1];
+    const bool head_valid = e0 > 0 && row[e0 - 1] == head_row;
+    const bool tail_valid = e1 < nnz && row[e1] == last_row && !(head_valid && head_row == last_row);
+    if (lane == 0) {
+        crow[2 * t] = head_valid ? head_row : -1;
+        crow[2 * t + 1] = tail_valid ? last_row : -1;
+    }
+    if (t == 0)                                                // empty rows before the first entry
+        for (int32_t r = lane; r < head_row; r += kWave)
+            for (int q = 0; q < KM; ++q)
+                if (KM == 1 || q < k) Y[(int64_t)r * ldy + q] = T(0);
+    int32_t carry_row = -1;                                    // row running on from the last chunk
+    T carry[KM];
+#pragma unroll
+    for (int q = 0; q < KM; ++q) carry[q] = T(0);
+    for (int64_t base = e0; base < e1; base += kWave) {       // uniform per wavefront
+        const int64_t e = base + lane;
+        const bool valid = e < e1;
+        uint32_t key = 0xffffffffu;
+        int32_t nr = 0;
+        T prod[KM];
+        if (valid) {
+            key = (uint32_t)ld_stream(row + e);
+            nr = e + 1 < nnz ? row[e + 1] : nrows;
+            const T a = ValLoad<V, T>::get(val + e);
+            const T *xr = X + (int64_t)ld_stream(col + e) * ldx;
+#pragma unroll
+            for (int q = 0; q < KM; ++q) prod[q] = (KM == 1 || q < k) ? a * xr[q] : T(0);
+        } else {
+#pragma unroll
+            for (int q = 0; q < KM; ++q) prod[q] = T(0);
+        }
+        if (lane == 0 && carry_row >= 0 && (uint32_t)carry_row == key) {
+#pragma unroll
+            for (int q = 0; q < KM; ++q) prod[q] += carry[q];
+        }
+#pragma unroll
+        for (int d = 1; d < kWave; d <<= 1) {                 // inclusive segmented scan by row
+            const uint32_t kd = __shfl_up(key, d);
+            const bool take = lane >= d && kd == key;
+#pragma unroll
+            for (int q = 0; q < KM; ++q) {
+                const T v = __shfl_up(prod[q], d);
+                if (take) prod[q] += v;
+            }
+        }
+        const uint32_t nxt = __shfl_down(key, 1);
+        const bool seg_end = valid && (lane == kWave - 1 || nxt != key);
+        const bool to_next = seg_end && e + 1 < e1 && nr == (int32_t)key;
+        carry_row = __shfl(to_next ? (int32_t)key : -1, kWave - 1);
+#pragma unroll
+        for (int q = 0; q < KM; ++q) carry[q] = __shfl(prod[q], kWave - 1);
+        if (seg_end && !to_next) {
+            const int32_t r = (int32_t)key;
+            if (head_valid && r == head_row) {
+#pragma unroll
+                for (int q = 0; q < KM; ++q) cval[(2 * t) * KM + q] = prod[q];
+            } else if (tail_valid && e == e1 - 1) {
+#pragma unroll
+                for (int q = 0; q < KM; ++q) cval[(2 * t + 1) * KM + q] = prod[q];
+            } else {
+#pragma unroll
+                for (int q = 0; q < KM; ++q)
+                    if (KM == 1 || q < k) Y[(int64_t)r * ldy + q] = prod[q];
+            }
+            for (int32_t z = r + 1; z < nr; ++z)               // empty rows up to the next entry's
+#pragma unroll
+                for (int q = 0; q < KM; ++q)
+                    if (KM == 1 || q < k) Y[(int64_t)z * ldy + q] = T(0);
+        }
+    }
+}
+
+// Each row cut by tile edges is owned by the tile where it starts (its tail):
+// that tile's partial, then the heads of the following tiles in order.
+template <typename T, int KM>
+__global__ __launch_bounds__(kBlock) void k_coo_fixup(int64_t ntiles, const int32_t *__restrict__ crow,
+                                                      const T *__restrict__ cval, int32_t k,
+                                                      T *__restrict__ Y, int64_t ldy) {
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < ntiles;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t r = crow[2 * t + 1];
+        if (r < 0) continue;
+        T sum[KM];
+#pragma unroll
+        for (int q = 0; q < KM; ++q) sum[q] = cval[(2 * t + 1) * KM + q];
+        for (int64_t u = t + 1; u < ntiles && crow[2 * u] == r; ++u)
+#pragma unroll
+            for (int q = 0; q < KM; ++q) sum[q] += cval[(2 * u) * KM + q];
+#pragma unroll
+        for (int q = 0; q < KM; ++q)
+            if (KM == 1 || q < k) Y[(int64_t)r * ldy + q] = sum[q];
+    }
+}
+
+template <typename V, typename T, int KM>
+hipError_t coo_launch(const SpmvArgs &a, hipStream_t s) {
+    if (!a.coo_row || !a.coo_ws) return hipErrorInvalidValue;
+    if (a.nnz == 0) {
+        hipLaunchKernelGGL((k_zero_rows<T, KM>), dim3((unsigned)std::min<int64_t>(cdiv((int64_t)a.nrows * a.k, kBlock), 4096)),
+                           dim3(kBlock), 0, s, a.nrows, a.k, (T *)a.Y, a.ldy);
+        return hipGetLastError();
+    }
+    const int64_t ntiles = cdiv(a.nnz, kCooTile);
+    int32_t *crow = (int32_t *)a.coo_ws;
+    T *cval = (T *)((char *)a.coo_ws + ((sizeof(int32_t) * 2 * ntiles + 255) & ~size_t(255)));
+    hipLaunchKernelGGL((k_spmv_coo<V, T, KM>), dim3((unsigned)cdiv(ntiles, kBlock / kWave)),
+                       dim3(kBlock), 0, s, a.nrows, a.nnz, a.coo_row, a.col, (const V *)a.val, a.k,
+                       (const T *)a.X, a.ldx, (T *)a.Y, a.ldy, crow, cval);
+    hipLaunchKernelGGL((k_coo_fixup<T, KM>), dim3((unsigned)std::min<int64_t>(cdiv(ntiles, kBlock), 4096)),
+                       dim3(kBlock), 0, s, ntiles, (const int32_t *)crow, (const T *)cval, a.k,
+                       (T *)a.Y, a.ldy);
+    return hipGetLastError();
+}
+
 // Persistent grid: each workgroup takes the next tile index from a device
 // counter until all tiles of all matrices are done; every workgroup reaches
 // the exit test, so the grid always drains. VT is the value type shared by
@@ -492,6 +652,7 @@ hipError_t spmv_k(const SpmvArgs &a, int variant, hipStream_t s) {
         if constexpr (KM <= 4) return merge_launch<V, T, KM>(a, s);
         return hipErrorInvalidValue;
     }
+    if (family == MXE_VAR_COO) return coo_launch<V, T, KM>(a, s);
     if (family == MXE_VAR_FIXED) {
         const int L = std::max(lanes, KM);
         const int32_t parts = kFixedParts;
@@ -518,6 +679,18 @@ hipError_t spmv_t(const SpmvArgs &a, int variant, hipStream_t s) {
 size_t merge_ws_bytes(int32_t nrows, int64_t nnz) {
     const int64_t ntiles = std::max<int64_t>(1, cdiv((int64_t)nrows + nnz, kMergeTile));
     return ((sizeof(Coord) * (ntiles + 1) + 255) & ~255ull) + sizeof(Carry) * ntiles + 256;
+}
+
+size_t coo_ws_bytes(int64_t nnz) {
+    const int64_t ntiles = std::max<int64_t>(1, cdiv(nnz, kCooTile));
+    return ((sizeof(int32_t) * 2 * ntiles + 255) & ~size_t(255)) + sizeof(double) * 2 * ntiles * 16;
+}
+
+hipError_t launch_coo_rows(int32_t nrows, const int32_t *rp, int32_t *row, hipStream_t s) {
+    if (nrows <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_coo_rows, dim3((unsigned)std::min<int64_t>(cdiv(nrows, kBlock), 16384)),
+                       dim3(kBlock), 0, s, nrows, rp, row);
+    return hipGetLastError();
 }
 
 hipError_t launch_spmv(const SpmvArgs &a, int variant, hipStream_t s) {

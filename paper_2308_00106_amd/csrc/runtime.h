@@ -49,6 +49,8 @@ struct Matrix {
     int32_t bin_off[kNumBins + 1] = {};
     bool bins_ready = false;
     void *merge_ws = nullptr;
+    int32_t *coo_row = nullptr;         // COO row index per entry (an entry of allocs)
+    void *coo_ws = nullptr;             // COO tile carries (an entry of allocs)
     struct Slab {
         SlabGeom g;
         int32_t *off = nullptr;

@@ -26,7 +26,7 @@ DTYPES = {"f64": F64, "f32": F32, "bf16": BF16}
 INPUT_DEVICE = OUTPUT_DEVICE = 0x1
 ROWS, COLS, GRADIENT = 0x1, 0x2, 0x4
 SPACE_PERMUTED, SPACE_ORIGINAL = 0x0, 0x1
-VAR_GROUP, VAR_BINNED, VAR_MERGE, VAR_SLAB, VAR_FIXED = 0x000, 0x100, 0x200, 0x300, 0x400
+VAR_GROUP, VAR_BINNED, VAR_MERGE, VAR_SLAB, VAR_FIXED, VAR_COO = 0x000, 0x100, 0x200, 0x300, 0x400, 0x500
 
 
 def variant(family: int, lanes: int = 0) -> int:

@@ -160,7 +160,7 @@ def test_entropy_rejects_bad_grid(ctx):
 VARIANTS = [mx.variant(mx.VAR_GROUP, lanes) for lanes in (1, 2, 4, 8, 16, 32, 64)] + \
            [mx.variant(mx.VAR_BINNED), mx.variant(mx.VAR_MERGE),
             mx.variant(mx.VAR_SLAB, 1), mx.variant(mx.VAR_SLAB, 32),   # 64 KiB and 2 MiB slabs
-            mx.variant(mx.VAR_FIXED, 4), mx.variant(mx.VAR_FIXED, 16)]
+            mx.variant(mx.VAR_FIXED, 4), mx.variant(mx.VAR_FIXED, 16), mx.variant(mx.VAR_COO)]
 
 
 def _force(ctx, H, k, v):
@@ -303,7 +303,8 @@ def test_full_size_config2(ctx):
 # --- hierarchical entropy, gradient formats, fixed partition ------------------------
 
 @pytest.mark.parametrize("case,grid", [("config1", (64, 64)), ("skewed", (64, 64)),
-                                       ("wide", (5, 1000)), ("ragged", (37, 23))])
+                                       ("wide", (5, 1000)), ("ragged", (37, 23)),
+                                       ("skewed", (1024, 1024))])    # several workgroups a region
 def test_entropy_levels_exact(ctx, case, grid):
     A0 = dict(CSR_CASES)[case]()
     A = ctx.register(A0)
@@ -357,4 +358,30 @@ def test_fixed_partition_variant(ctx):
             torch.cuda.synchronize()
             assert spmv_error(Ho, x, Y.cpu().numpy(), "f64") <= TOL["f64"], lanes
     ctx.release(B)
+    ctx.release(A)
+
+
+def test_coo_rows_across_many_tiles(ctx):
+    """COO tiles cut rows: one row of 5000 entries (20 tiles), rows of 300,
+    runs of empty rows at both ends and between."""
+    rng = np.random.default_rng(17)
+    lens = np.zeros(3000, np.int64)
+    lens[5] = 5000
+    lens[100:140] = 300
+    lens[1000:2990:7] = rng.integers(1, 40, size=len(range(1000, 2990, 7)))
+    rows = np.repeat(np.arange(3000), lens)
+    cols = np.concatenate([rng.choice(6000, size=L, replace=False) for L in lens if L])
+    A0 = synth.from_entries(3000, 6000, rows, cols, rng.uniform(-1, 1, len(rows)))
+    A = ctx.register(A0)
+    ctx.set_variant(A, 2, mx.variant(mx.VAR_COO))
+    for k in (1, 2):
+        X = synth.vector(A0.ncols, 5, k=k)
+        Y = torch.full((A0.nrows, k) if k > 1 else (A0.nrows,), float("nan"),
+                       dtype=torch.float64, device="cuda")
+        ctx.set_variant(A, k, mx.variant(mx.VAR_COO))
+        ctx.spmv(A, torch_vec(X, torch.float64), Y)
+        torch.cuda.synchronize()
+        assert spmv_error(A0, X, Y.cpu().numpy(), "f64") <= TOL["f64"], k
+        ref = oracle.coo_spmm(A0.nrows, oracle.coo_rows(A0.row_ptr), A0.col, A0.val, X)
+        assert np.array_equal(Y.cpu().numpy()[lens == 0], ref[lens == 0])    # exact zeros
     ctx.release(A)

@@ -284,6 +284,33 @@ def test_spmm_columns_equal_spmv_and_scipy():
     assert err < 1e-15
 
 
+def test_coo_rows_expand_row_ptr():
+    rp = np.array([0, 2, 2, 5, 6], np.int32)
+    assert oracle.coo_rows(rp).tolist() == [0, 0, 2, 2, 2, 3]
+    assert oracle.coo_rows(np.array([0], np.int32)).tolist() == []
+
+
+def test_coo_spmv_dense_brute_force_and_scipy():
+    A = synth.random_csr(40, 33, 0.3, 8, empty_rows=0.2)
+    D = _dense(A)
+    x = synth.vector(33, 9)
+    row = oracle.coo_rows(A.row_ptr)
+    y = oracle.coo_spmm(A.nrows, row, A.col, A.val, x)
+    for i in range(40):                 # sorted COO: each row's terms in increasing column
+        acc = 0.0
+        for j in range(33):
+            acc += D[i, j] * x[j]
+        assert y[i] == acc
+    # entries in any order: the same matrix, within rounding of scipy's COO product
+    import scipy.sparse as sp
+    perm = np.random.default_rng(3).permutation(A.nnz)
+    X = synth.vector(33, 10, k=3)
+    Y = oracle.coo_spmm(A.nrows, row[perm], A.col[perm], A.val[perm], X)
+    ref = sp.coo_matrix((A.val[perm], (row[perm], A.col[perm])), shape=(40, 33)) @ X
+    assert oracle.normalized_error(A.nrows, A.row_ptr, A.col, A.val, X, Y, ref) < 1e-15
+    assert np.all(Y[np.diff(A.row_ptr) == 0] == 0.0)   # empty rows are exactly zero
+
+
 def test_spmm_parallel_equals_serial():
     A = synth.random_csr(500, 300, 0.05, 12)
     X = np.ascontiguousarray(synth.vector(300, 13, k=3))
