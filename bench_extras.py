@@ -9,9 +9,10 @@
               launch replayed from a HIP graph.
   heavy       2,000,000-row CSR, 8 nnz per row except one contiguous band of
               1% of the rows with 512 each (heavy clustered rows): SpMV with
-              the fixed equal-row partition (no counting) and with the tuned
-              count-aware variant on the original, R, RC and gradient (G-R,
-              G-RC) orderings, plus the hierarchical 2D entropy of each.
+              the fixed equal-row partition (no counting), the COO kernel and
+              the tuned count-aware variant on the original, R, RC and
+              gradient (G-R, G-RC) orderings, plus the hierarchical 2D
+              entropy of each.
   serving     32 resident permuted matrices of 50k-2M rows (FP32), requests of
               1-8 right-hand sides on a random matrix; closed-loop saturation
               rate, then open-loop Poisson arrivals at 0.5 and 0.8 of it:
@@ -104,6 +105,8 @@ def heavy(ctx, log, n=2_000_000, reps=50):
             ctx.set_variant(H, 1, mx.variant(mx.VAR_FIXED, lanes))
             us = _time(ctx, H, xt, y, reps, stream)
             r[f"fixed_l{lanes}_us"] = round(us, 2)
+        ctx.set_variant(H, 1, mx.variant(mx.VAR_COO))     # 16 B per entry: row, column, value
+        r["coo_us"] = round(_time(ctx, H, xt, y, reps, stream), 2)
         v = ctx.tune(H, 1, stream=stream)
         us = _time(ctx, H, xt, y, reps, stream)
         r["tuned_us"] = round(us, 2)

@@ -8,7 +8,7 @@ function of its seed.
 The paper measures on SuiteSparse matrices (OPF 3754, LP OSA 07, MULT DCOP
 01/03; Section 6) that are not available here. The generators below stand in
 for them with the structures the paper describes: a mostly block-diagonal
-matrix whose x reads fall "in close quarters" (Section 6, OPF 3754), and rows
+matrix whose x reads stay close together (Section 7, OPF 3754), and rows
 of skewed length clustered near the diagonal (LP OSA 07's heavy clustered
 rows). Dense rows or columns are excluded, as Section 1 requires.
 """
