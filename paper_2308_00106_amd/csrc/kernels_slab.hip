@@ -17,7 +17,8 @@
 // (workgroups are dealt to the 8 XCDs round-robin), so at any moment an XCD's
 // workgroups gather from one slab of x that sits in its L2. Because a
 // max-entropy matrix gives every (block, slab) tile the same expected nonzero
-// count, the workgroups of an XCD stay in step. Each row's sum is taken in a
+// count, the workgroups of an XCD stay in step; a barrier after each slab
+// keeps the wavefronts of a workgroup together. Each row's sum is taken in a
 // fixed order (slabs in rotation order, entries in storage order, a fixed
 // segmented scan inside a wavefront), so results are deterministic.
 #include "device_common.h"
@@ -147,7 +148,74 @@ template <> struct SlabVal<uint16_t, float> {
     __device__ static float get(uint16_t v) { return bf16_to_f32(v); }
 };
 
-// The product. LDS holds the block's partial y (rows_per_block x KM).
+// Inclusive segmented scan over a wavefront whose keys never decrease
+// (equal keys are adjacent), on DPP lane moves instead of LDS permutes:
+// four row_shr steps inside each row of 16 lanes, then row_bcast:15 into rows
+// 1 and 3 and row_bcast:31 into rows 2 and 3. A lane adds the moved value only
+// when it carries its own key; moves from outside a row read key 0 and value
+// 0 (adding nothing), and rows a broadcast skips keep a key no row can have.
+template <int CTRL>
+__device__ inline uint32_t dpp_shr_u32(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, CTRL, 0xf, 0xf, true);
+}
+template <int CTRL, int RMASK>
+__device__ inline uint32_t dpp_bcast_u32(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_update_dpp((int)0xfffffffeu, (int)v, CTRL, RMASK, 0xf, false);
+}
+template <int CTRL>
+__device__ inline double dpp_shr(double v) {
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xf, 0xf, true);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xf, 0xf, true);
+    return __hiloint2double(hi, lo);
+}
+template <int CTRL>
+__device__ inline float dpp_shr(float v) {
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xf, 0xf, true));
+}
+template <int CTRL, int RMASK>
+__device__ inline double dpp_bcast(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, RMASK, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, RMASK, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+template <int CTRL, int RMASK>
+__device__ inline float dpp_bcast(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, RMASK, 0xf, false));
+}
+
+template <int CTRL, typename T, int KM>
+__device__ inline void scan_shr(uint32_t key, T (&v)[KM]) {
+    const bool take = dpp_shr_u32<CTRL>(key) == key;
+#pragma unroll
+    for (int q = 0; q < KM; ++q) {
+        const T m = dpp_shr<CTRL>(v[q]);
+        v[q] += take ? m : T(0);
+    }
+}
+template <int CTRL, int RMASK, typename T, int KM>
+__device__ inline void scan_bcast(uint32_t key, T (&v)[KM]) {
+    const bool take = dpp_bcast_u32<CTRL, RMASK>(key) == key;
+#pragma unroll
+    for (int q = 0; q < KM; ++q) {
+        const T m = dpp_bcast<CTRL, RMASK>(v[q]);
+        v[q] += take ? m : T(0);
+    }
+}
+template <typename T, int KM>
+__device__ inline void segmented_scan(uint32_t key, T (&v)[KM]) {
+    scan_shr<0x111>(key, v);            // row_shr:1
+    scan_shr<0x112>(key, v);            // row_shr:2
+    scan_shr<0x114>(key, v);            // row_shr:4
+    scan_shr<0x118>(key, v);            // row_shr:8
+    scan_bcast<0x142, 0xa>(key, v);     // row_bcast:15 -> rows 1, 3
+    scan_bcast<0x143, 0xc>(key, v);     // row_bcast:31 -> rows 2, 3
+}
+
+// The product. LDS holds the block's partial y (rows_per_block x KM). The
+// workgroup walks the slabs in its rotation together (a barrier after each
+// slab), so all its wavefronts gather from the same L2-resident x slice;
+// inside a slab a wavefront loads up to Unroll chunks of its group at once,
+// issues their x gathers together, then reduces each chunk by row.
 template <typename V, typename T, int KM>
 __global__ __launch_bounds__(kSlabBlock) void k_spmv_slab(SlabGeom g, const int32_t *__restrict__ off,
                                                           const uint32_t *__restrict__ idx,
@@ -159,9 +227,8 @@ __global__ __launch_bounds__(kSlabBlock) void k_spmv_slab(SlabGeom g, const int3
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     const int32_t R = g.rows_per_block;
     for (int i = threadIdx.x; i < R * KM; i += kSlabBlock) yp[i] = T(0);
-    __syncthreads();
     T *ywave = yp + (int64_t)wave * g.rows_per_sub * KM;
-    // This wavefront's groups (one per slab) and their offsets, staged in LDS.
+    // this wavefront's groups (one per slab) and their offsets, staged in LDS
     __shared__ int32_t soff[kSubBlocks][kSlabMax + 1];
     const int32_t *o = off + ((int64_t)blockIdx.x * kSubBlocks + wave) * g.slabs;
     for (int s = lane; s <= g.slabs; s += kWave) soff[wave][s] = o[s];
@@ -169,83 +236,50 @@ __global__ __launch_bounds__(kSlabBlock) void k_spmv_slab(SlabGeom g, const int3
     const int xcd = blockIdx.x % 8;
     const int s0 = (int)(((int64_t)xcd * g.slabs) / 8);
     const uint32_t cmask = (1u << g.cbits) - 1u;
-    // Chunk iterator (wavefront-uniform): 64-entry chunks, never straddling a
-    // group, so rows rise monotonically inside every chunk and a row has at
-    // most one segment per chunk. Groups are visited in rotation from s0.
-    int t = 0, s = s0;
-    int32_t c = soff[wave][s0], e = soff[wave][s0 + 1];
-    auto next_chunk = [&](int32_t &start, int32_t &cnt) -> bool {
-        while (c >= e) {
-            if (++t >= g.slabs) return false;
-            s = s0 + t < g.slabs ? s0 + t : s0 + t - g.slabs;
-            c = soff[wave][s];
-            e = soff[wave][s + 1];
-        }
-        start = c;
-        cnt = min(kWave, e - c);
-        c += kWave;
-        return true;
-    };
-    // Software pipeline over kDepth register slots: a slot's index and value
-    // loads are issued kDepth chunks before the slot is reduced.
-    constexpr int kDepth = Unroll<KM>::value;
-    uint32_t u[kDepth];
-    T a[kDepth];
-    bool live[kDepth];
+    constexpr int kD = Unroll<KM>::value;
+    for (int t = 0; t < g.slabs; ++t) {                       // same count in every wavefront
+        const int s = s0 + t < g.slabs ? s0 + t : s0 + t - g.slabs;
+        const int32_t e = soff[wave][s + 1];
+        for (int32_t c = soff[wave][s]; c < e; c += kD * kWave) {
+            uint32_t u[kD];
+            T a[kD];
+            T xv[kD][KM];
 #pragma unroll
-    for (int j = 0; j < kDepth; ++j) {
-        int32_t st = 0, n = 0;
-        live[j] = next_chunk(st, n);
-        const bool v = live[j] && lane < n;
-        u[j] = v ? __builtin_nontemporal_load(idx + st + lane) : 0xffffffffu;
-        a[j] = v ? SlabVal<V, T>::get(__builtin_nontemporal_load(val + st + lane)) : T(0);
-    }
-    bool more = live[0];
-    while (more) {
-#pragma unroll
-        for (int j = 0; j < kDepth; ++j) {
-            if (!live[j]) {
-                more = false;
-                break;
+            for (int j = 0; j < kD; ++j) {
+                const int32_t p = c + j * kWave + lane;
+                const bool v = p < e;
+                u[j] = v ? idx[p] : 0xffffffffu;
+                a[j] = v ? SlabVal<V, T>::get(val[p]) : T(0);
             }
-            const bool valid = u[j] != 0xffffffffu;
-            const uint32_t key = valid ? (u[j] >> g.cbits) : 0xffffffffu;
-            const T *xr = X + (int64_t)(valid ? (u[j] & cmask) : 0) * ldx;
-            T prod[KM];
 #pragma unroll
-            for (int q = 0; q < KM; ++q)
-                prod[q] = (valid && (KM == 1 || q < k)) ? a[j] * xr[q] : T(0);
-            {   // refill the slot with the chunk kDepth ahead
-                int32_t st = 0, n = 0;
-                live[j] = next_chunk(st, n);
-                const bool v = live[j] && lane < n;
-                u[j] = v ? __builtin_nontemporal_load(idx + st + lane) : 0xffffffffu;
-                a[j] = v ? SlabVal<V, T>::get(__builtin_nontemporal_load(val + st + lane)) : T(0);
+            for (int j = 0; j < kD; ++j) {
+                const bool v = u[j] != 0xffffffffu;
+                const T *xr = X + (int64_t)(v ? (u[j] & cmask) : 0) * ldx;
+#pragma unroll
+                for (int q = 0; q < KM; ++q) xv[j][q] = (v && (KM == 1 || q < k)) ? xr[q] : T(0);
             }
-            // inclusive segmented scan by row; padding lanes (key 0xffffffff)
-            // sit after every valid lane
 #pragma unroll
-            for (int d = 1; d < kWave; d <<= 1) {
-                const uint32_t kd = __shfl_up(key, d);
-                const bool take = lane >= d && kd == key;
+            for (int j = 0; j < kD; ++j) {
+                if (c + j * kWave >= e) break;                // uniform per wavefront
+                // padding lanes (key 0xffffffff) sit after every valid lane
+                const uint32_t key = u[j] != 0xffffffffu ? (u[j] >> g.cbits) : 0xffffffffu;
+                T prod[KM];
 #pragma unroll
-                for (int q = 0; q < KM; ++q) {
-                    const T v = __shfl_up(prod[q], d);
-                    if (take) prod[q] += v;
+                for (int q = 0; q < KM; ++q) prod[q] = a[j] * xv[j][q];
+                segmented_scan<T, KM>(key, prod);
+                const uint32_t nxt = __shfl_down(key, 1);
+                const bool tail = key != 0xffffffffu && (lane == kWave - 1 || nxt != key);
+                if (tail) {
+#pragma unroll
+                    for (int q = 0; q < KM; ++q) ywave[(int64_t)key * KM + q] += prod[q];
                 }
+                // the next chunk's tails may update the same rows: keep order
+                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                __builtin_amdgcn_wave_barrier();
             }
-            const uint32_t nxt = __shfl_down(key, 1);
-            const bool tail = key != 0xffffffffu && (lane == kWave - 1 || nxt != key);
-            if (tail) {
-#pragma unroll
-                for (int q = 0; q < KM; ++q) ywave[(int64_t)key * KM + q] += prod[q];
-            }
-            // the next chunk's tails may update the same rows: keep order
-            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-            __builtin_amdgcn_wave_barrier();
         }
+        __syncthreads();
     }
-    __syncthreads();
     const int64_t row0 = (int64_t)blockIdx.x * R;
     for (int i = threadIdx.x; i < R * KM; i += kSlabBlock) {
         const int64_t row = row0 + i / KM;
