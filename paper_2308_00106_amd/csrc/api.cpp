@@ -265,8 +265,8 @@ static mxe_status prepare_args(mxe_ctx *ctx, Matrix &A, int variant, int32_t k, 
 }
 
 // ---- autotuner ---------------------------------------------------------------------
-// Times every variant (GROUP with 1..64 lanes, BINNED, MERGE when k <= 4,
-// SLAB with 1, 2 and 4 MiB slabs when the layout fits) on the matrix itself
+// Times every variant (GROUP with 1..64 lanes, BINNED, FIXED, MERGE when
+// k <= 4, SLAB with 0.75, 1, 2 and 4 MiB slabs when the layout fits) on the matrix itself
 // with scratch vectors and keeps the fastest; also keeps the fastest GROUP
 // lanes for the persistent batch kernel.
 static mxe_status tune(mxe_ctx *ctx, Matrix &A, int32_t k, hipStream_t s, TuneResult *out) {
@@ -282,7 +282,7 @@ static mxe_status tune(mxe_ctx *ctx, Matrix &A, int32_t k, hipStream_t s, TuneRe
     cands.push_back(MXE_VARIANT(MXE_VAR_BINNED, 0));
     cands.push_back(MXE_VARIANT(MXE_VAR_FIXED, std::max(kc, 8)));
     if (kc <= 4) cands.push_back(MXE_VARIANT(MXE_VAR_MERGE, 0));
-    for (int units : {16, 32, 64}) {                 // 1, 2 and 4 MiB of x per slab
+    for (int units : {12, 16, 32, 64}) {             // 0.75, 1, 2 and 4 MiB of x per slab
         SlabGeom g;
         if (slab_geometry(A.nrows, A.ncols, kc, vtype_of(A.storage), ctx->cu_count,
                           slab_bytes_of(units), &g))

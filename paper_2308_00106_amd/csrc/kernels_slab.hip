@@ -215,7 +215,8 @@ __device__ inline void segmented_scan(uint32_t key, T (&v)[KM]) {
 // workgroup walks the slabs in its rotation together (a barrier after each
 // slab), so all its wavefronts gather from the same L2-resident x slice;
 // inside a slab a wavefront loads up to Unroll chunks of its group at once,
-// issues their x gathers together, then reduces each chunk by row.
+// issues their x gathers together, then reduces each chunk by row. The first
+// batch of the next slab's group is loaded before each barrier.
 template <typename V, typename T, int KM>
 __global__ __launch_bounds__(kSlabBlock) void k_spmv_slab(SlabGeom g, const int32_t *__restrict__ off,
                                                           const uint32_t *__restrict__ idx,
@@ -237,20 +238,24 @@ __global__ __launch_bounds__(kSlabBlock) void k_spmv_slab(SlabGeom g, const int3
     const int s0 = (int)(((int64_t)xcd * g.slabs) / 8);
     const uint32_t cmask = (1u << g.cbits) - 1u;
     constexpr int kD = Unroll<KM>::value;
+    uint32_t u[kD];
+    T a[kD];
+    auto load_batch = [&](int32_t c, int32_t e) {             // up to kD chunks of [c, e)
+#pragma unroll
+        for (int j = 0; j < kD; ++j) {
+            const int32_t p = c + j * kWave + lane;
+            const bool v = p < e;
+            u[j] = v ? idx[p] : 0xffffffffu;
+            a[j] = v ? SlabVal<V, T>::get(val[p]) : T(0);
+        }
+    };
+    load_batch(soff[wave][s0], soff[wave][s0 + 1]);
     for (int t = 0; t < g.slabs; ++t) {                       // same count in every wavefront
         const int s = s0 + t < g.slabs ? s0 + t : s0 + t - g.slabs;
-        const int32_t e = soff[wave][s + 1];
-        for (int32_t c = soff[wave][s]; c < e; c += kD * kWave) {
-            uint32_t u[kD];
-            T a[kD];
+        const int32_t b = soff[wave][s], e = soff[wave][s + 1];
+        for (int32_t c = b; c < e; c += kD * kWave) {
+            if (c != b) load_batch(c, e);                     // the first batch is already loaded
             T xv[kD][KM];
-#pragma unroll
-            for (int j = 0; j < kD; ++j) {
-                const int32_t p = c + j * kWave + lane;
-                const bool v = p < e;
-                u[j] = v ? idx[p] : 0xffffffffu;
-                a[j] = v ? SlabVal<V, T>::get(val[p]) : T(0);
-            }
 #pragma unroll
             for (int j = 0; j < kD; ++j) {
                 const bool v = u[j] != 0xffffffffu;
@@ -277,6 +282,10 @@ __global__ __launch_bounds__(kSlabBlock) void k_spmv_slab(SlabGeom g, const int3
                 __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
                 __builtin_amdgcn_wave_barrier();
             }
+        }
+        if (t + 1 < g.slabs) {                                // next slab's first batch, issued
+            const int sn = s + 1 < g.slabs ? s + 1 : 0;       // before the barrier waits
+            load_batch(soff[wave][sn], soff[wave][sn + 1]);
         }
         __syncthreads();
     }
