@@ -629,7 +629,7 @@ mxe_status mxe_permute(mxe_ctx *ctx, mxe_mat a, uint64_t seed, uint32_t mode, vo
         MXE_HIP(launch_iota_i32(B->cinv, N, s));
     }
     MXE_HIP(launch_permuted_row_ptr(M, A->rp, B->rperm, B->rp, ws.p, s));
-    MXE_HIP(launch_gather_relabel_sort(M, A->rp, A->col, A->val, vb, B->rperm,
+    MXE_HIP(launch_gather_relabel_sort(M, A->rp, A->col, A->val, vb, B->rinv,
                                        (mode & MXE_COLS) ? B->cinv : nullptr, B->rp, B->col,
                                        B->val, s));
     B->id = ctx->next_id++;

@@ -41,10 +41,11 @@ hipError_t launch_gradient_perm(int64_t n, const int32_t *counts, uint64_t strea
 size_t permuted_row_ptr_ws_bytes(int32_t nrows);
 hipError_t launch_permuted_row_ptr(int32_t nrows, const int32_t *rp, const int32_t *rperm,
                                    int32_t *rp_b, void *ws, hipStream_t s);
-// Row i' of B <- row rperm[i'] of A with column j -> cinv[j] (cinv may be
-// NULL: no column permutation), re-sorted by new column. val_bytes: 8, 4, 2.
+// Row i of A -> row rinv[i] of B (at rp_b[rinv[i]]) with column j -> cinv[j]
+// (cinv may be NULL: no column permutation), re-sorted by new column.
+// val_bytes: 8, 4, 2.
 hipError_t launch_gather_relabel_sort(int32_t nrows, const int32_t *rp, const int32_t *col,
-                                      const void *val, int val_bytes, const int32_t *rperm,
+                                      const void *val, int val_bytes, const int32_t *rinv,
                                       const int32_t *cinv, const int32_t *rp_b, int32_t *col_b,
                                       void *val_b, hipStream_t s);
 

@@ -216,23 +216,25 @@ constexpr int kSortCap = 256;                           // columns staged in LDS
 // Each group of 16 lanes moves one row: relabels its columns through cinv,
 // stages them in LDS, and places every entry at its rank among the row's new
 // columns (distinct, so the rank is its sorted position). Rows longer than the
-// LDS stage read the relabelled columns straight from memory.
+// LDS stage read the relabelled columns straight from memory. Rows are taken
+// in A's order and written to their place in B (row i goes to rinv[i]): the
+// reads stream, and a matrix whose columns cluster by row keeps its cinv
+// lookups in cache from one row to the next.
 template <typename V>
 __global__ __launch_bounds__(kBlock) void k_gather_relabel_sort(
     int32_t nrows, const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
-    const V *__restrict__ val, const int32_t *__restrict__ rperm, const int32_t *__restrict__ cinv,
+    const V *__restrict__ val, const int32_t *__restrict__ rinv, const int32_t *__restrict__ cinv,
     const int32_t *__restrict__ rp_b, int32_t *__restrict__ col_b, V *__restrict__ val_b) {
     __shared__ int32_t stage[kSortRows][kSortCap];
     const int g = threadIdx.x / kSortGroup, t0 = threadIdx.x % kSortGroup;
     for (int64_t base = (int64_t)blockIdx.x * kSortRows; base < nrows;
          base += (int64_t)gridDim.x * kSortRows) {
-        const int64_t row = base + g;
+        const int64_t row = base + g;                   // a row of A
         int32_t s0 = 0, len = 0, d0 = 0;
         if (row < nrows) {
-            const int32_t src = rperm[row];
-            s0 = rp[src];
-            len = rp[src + 1] - s0;
-            d0 = rp_b[row];
+            s0 = rp[row];
+            len = rp[row + 1] - s0;
+            d0 = rp_b[rinv[row]];
         }
         if (cinv == nullptr) {                          // rows only: order unchanged
             for (int32_t t = t0; t < len; t += kSortGroup) {
@@ -509,7 +511,7 @@ hipError_t launch_permuted_row_ptr(int32_t nrows, const int32_t *rp, const int32
 }
 
 hipError_t launch_gather_relabel_sort(int32_t nrows, const int32_t *rp, const int32_t *col,
-                                      const void *val, int val_bytes, const int32_t *rperm,
+                                      const void *val, int val_bytes, const int32_t *rinv,
                                       const int32_t *cinv, const int32_t *rp_b, int32_t *col_b,
                                       void *val_b, hipStream_t s) {
     if (nrows <= 0) return hipSuccess;
@@ -517,15 +519,15 @@ hipError_t launch_gather_relabel_sort(int32_t nrows, const int32_t *rp, const in
     switch (val_bytes) {
     case 8:
         hipLaunchKernelGGL(k_gather_relabel_sort<uint64_t>, dim3(g), dim3(kBlock), 0, s, nrows, rp,
-                           col, (const uint64_t *)val, rperm, cinv, rp_b, col_b, (uint64_t *)val_b);
+                           col, (const uint64_t *)val, rinv, cinv, rp_b, col_b, (uint64_t *)val_b);
         break;
     case 4:
         hipLaunchKernelGGL(k_gather_relabel_sort<uint32_t>, dim3(g), dim3(kBlock), 0, s, nrows, rp,
-                           col, (const uint32_t *)val, rperm, cinv, rp_b, col_b, (uint32_t *)val_b);
+                           col, (const uint32_t *)val, rinv, cinv, rp_b, col_b, (uint32_t *)val_b);
         break;
     case 2:
         hipLaunchKernelGGL(k_gather_relabel_sort<uint16_t>, dim3(g), dim3(kBlock), 0, s, nrows, rp,
-                           col, (const uint16_t *)val, rperm, cinv, rp_b, col_b, (uint16_t *)val_b);
+                           col, (const uint16_t *)val, rinv, cinv, rp_b, col_b, (uint16_t *)val_b);
         break;
     default:
         return hipErrorInvalidValue;
