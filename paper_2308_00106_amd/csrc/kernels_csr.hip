@@ -209,56 +209,85 @@ __global__ __launch_bounds__(kBlock) void k_perm_row_len(int32_t nrows, const in
     }
 }
 
-constexpr int kSortGroup = 16;                          // lanes per row
-constexpr int kSortRows = kBlock / kSortGroup;          // rows per workgroup step
-constexpr int kSortCap = 256;                           // columns staged in LDS per row
+constexpr int kSortRows = 16;                           // rows of A per wavefront
+constexpr int kSortStage = 1024;                        // staged entries per wavefront
+constexpr int kSortWaves = kBlock / kWave;
 
-// Each group of 16 lanes moves one row: relabels its columns through cinv,
-// stages them in LDS, and places every entry at its rank among the row's new
-// columns (distinct, so the rank is its sorted position). Rows longer than the
-// LDS stage read the relabelled columns straight from memory. Rows are taken
-// in A's order and written to their place in B (row i goes to rinv[i]): the
-// reads stream, and a matrix whose columns cluster by row keeps its cinv
-// lookups in cache from one row to the next.
+// Each wavefront moves kSortRows consecutive rows of A (row i goes to row
+// rinv[i] of B, at rp_b[rinv[i]]): it stages the rows' relabelled columns
+// (j -> cinv[j]) in LDS, then every lane takes entries, finds each one's row
+// by binary search over the staged row starts, and writes it at its rank among
+// its row's new columns (distinct, so the rank is its sorted position). Reads
+// stream through A in order, so a matrix whose columns cluster by row keeps
+// its cinv lookups in cache. Groups of rows with more than kSortStage entries
+// are moved one row at a time; a row longer than the stage ranks against
+// cinv in memory.
 template <typename V>
 __global__ __launch_bounds__(kBlock) void k_gather_relabel_sort(
     int32_t nrows, const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
     const V *__restrict__ val, const int32_t *__restrict__ rinv, const int32_t *__restrict__ cinv,
     const int32_t *__restrict__ rp_b, int32_t *__restrict__ col_b, V *__restrict__ val_b) {
-    __shared__ int32_t stage[kSortRows][kSortCap];
-    const int g = threadIdx.x / kSortGroup, t0 = threadIdx.x % kSortGroup;
-    for (int64_t base = (int64_t)blockIdx.x * kSortRows; base < nrows;
-         base += (int64_t)gridDim.x * kSortRows) {
-        const int64_t row = base + g;                   // a row of A
-        int32_t s0 = 0, len = 0, d0 = 0;
-        if (row < nrows) {
-            s0 = rp[row];
-            len = rp[row + 1] - s0;
-            d0 = rp_b[rinv[row]];
-        }
-        if (cinv == nullptr) {                          // rows only: order unchanged
-            for (int32_t t = t0; t < len; t += kSortGroup) {
-                col_b[d0 + t] = col[s0 + t];
-                val_b[d0 + t] = val[s0 + t];
+    __shared__ int32_t stage[kSortWaves][kSortStage];
+    __shared__ int32_t rstart[kSortWaves][kSortRows + 1];   // row starts, relative to e0
+    __shared__ int32_t rdest[kSortWaves][kSortRows];        // where each row goes in B
+    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    const int64_t r0 = ((int64_t)blockIdx.x * kSortWaves + wave) * kSortRows;
+    if (r0 >= nrows) return;                            // uniform per wavefront
+    const int nr = (int)std::min<int64_t>(kSortRows, nrows - r0);
+    const int32_t e0 = rp[r0];
+    if (lane <= nr) rstart[wave][lane] = rp[r0 + lane] - e0;
+    if (lane < nr) rdest[wave][lane] = rp_b[rinv[r0 + lane]];
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    const int32_t n = rstart[wave][nr];
+    auto relabel = [&](int32_t j) { return cinv ? cinv[j] : j; };
+    if (n <= kSortStage) {
+        for (int32_t i = lane; i < n; i += kWave) stage[wave][i] = relabel(col[e0 + i]);
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        for (int32_t i = lane; i < n; i += kWave) {
+            int lo = 0, hi = nr - 1;                    // last row whose start is <= i
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (rstart[wave][mid] <= i) lo = mid;
+                else hi = mid - 1;
             }
-            continue;
+            const int32_t b = rstart[wave][lo], e = rstart[wave][lo + 1];
+            const int32_t c = stage[wave][i];
+            int32_t r = i - b;                          // rows only: order unchanged
+            if (cinv) {
+                r = 0;
+                for (int32_t u = b; u < e; ++u) r += stage[wave][u] < c;
+            }
+            col_b[rdest[wave][lo] + r] = c;
+            val_b[rdest[wave][lo] + r] = val[e0 + i];
         }
-        const bool staged = len <= kSortCap;
+        return;
+    }
+    for (int j = 0; j < nr; ++j) {                      // one row at a time
+        const int32_t b = e0 + rstart[wave][j], len = rstart[wave][j + 1] - rstart[wave][j];
+        const int32_t d0 = rdest[wave][j];
+        const bool staged = len <= kSortStage;
         if (staged)
-            for (int32_t t = t0; t < len; t += kSortGroup) stage[g][t] = cinv[col[s0 + t]];
-        __syncthreads();
-        for (int32_t t = t0; t < len; t += kSortGroup) {
-            const int32_t c = staged ? stage[g][t] : cinv[col[s0 + t]];
-            int32_t r = 0;
-            if (staged) {
-                for (int32_t u = 0; u < len; ++u) r += stage[g][u] < c;
-            } else {
-                for (int32_t u = 0; u < len; ++u) r += cinv[col[s0 + u]] < c;
+            for (int32_t t = lane; t < len; t += kWave) stage[wave][t] = relabel(col[b + t]);
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        for (int32_t t = lane; t < len; t += kWave) {
+            const int32_t c = staged ? stage[wave][t] : relabel(col[b + t]);
+            int32_t r = t;
+            if (cinv) {
+                r = 0;
+                if (staged) {
+                    for (int32_t u = 0; u < len; ++u) r += stage[wave][u] < c;
+                } else {
+                    for (int32_t u = 0; u < len; ++u) r += cinv[col[b + u]] < c;
+                }
             }
             col_b[d0 + r] = c;
-            val_b[d0 + r] = val[s0 + t];
+            val_b[d0 + r] = val[b + t];
         }
-        __syncthreads();
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
     }
 }
 
@@ -515,18 +544,18 @@ hipError_t launch_gather_relabel_sort(int32_t nrows, const int32_t *rp, const in
                                       const int32_t *cinv, const int32_t *rp_b, int32_t *col_b,
                                       void *val_b, hipStream_t s) {
     if (nrows <= 0) return hipSuccess;
-    const int g = grid_for(nrows, kSortRows, 16384);
+    const int64_t g = cdiv(nrows, (int64_t)kSortRows * kSortWaves);
     switch (val_bytes) {
     case 8:
-        hipLaunchKernelGGL(k_gather_relabel_sort<uint64_t>, dim3(g), dim3(kBlock), 0, s, nrows, rp,
+        hipLaunchKernelGGL(k_gather_relabel_sort<uint64_t>, dim3((unsigned)g), dim3(kBlock), 0, s, nrows, rp,
                            col, (const uint64_t *)val, rinv, cinv, rp_b, col_b, (uint64_t *)val_b);
         break;
     case 4:
-        hipLaunchKernelGGL(k_gather_relabel_sort<uint32_t>, dim3(g), dim3(kBlock), 0, s, nrows, rp,
+        hipLaunchKernelGGL(k_gather_relabel_sort<uint32_t>, dim3((unsigned)g), dim3(kBlock), 0, s, nrows, rp,
                            col, (const uint32_t *)val, rinv, cinv, rp_b, col_b, (uint32_t *)val_b);
         break;
     case 2:
-        hipLaunchKernelGGL(k_gather_relabel_sort<uint16_t>, dim3(g), dim3(kBlock), 0, s, nrows, rp,
+        hipLaunchKernelGGL(k_gather_relabel_sort<uint16_t>, dim3((unsigned)g), dim3(kBlock), 0, s, nrows, rp,
                            col, (const uint16_t *)val, rinv, cinv, rp_b, col_b, (uint16_t *)val_b);
         break;
     default:
