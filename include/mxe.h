@@ -237,8 +237,9 @@ typedef struct mxe_item {
     uint32_t flags;             /* MXE_SPACE_PERMUTED only in batches */
 } mxe_item;
 
-/* One persistent launch computes every item: workgroups pull (item, row tile)
- * descriptors from a device work list. */
+/* One persistent launch computes every item: the items are dealt to one work
+ * queue per XCD (largest first onto the least loaded), and workgroups pull
+ * (item, row tile) work from their own XCD's queue, then from the others. */
 mxe_status mxe_spmv_batch(mxe_ctx *ctx, int32_t count, const mxe_item *items, void *stream);
 
 /* Plans a batch once (autotunes each item, builds the work list) and captures

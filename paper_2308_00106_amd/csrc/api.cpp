@@ -482,7 +482,7 @@ mxe_status mxe_destroy(mxe_ctx *ctx) {
             if (p.graph) (void)hipGraphDestroy(p.graph);
             if (p.capture_stream) (void)hipStreamDestroy(p.capture_stream);
             if (p.descs_dev) (void)hipFree(p.descs_dev);
-            if (p.counter) (void)hipFree(p.counter);
+            if (p.counters) (void)hipFree(p.counters);
         }
         ctx->plans.clear();
         ctx->mats.clear();
@@ -909,10 +909,44 @@ mxe_status mxe_set_variant(mxe_ctx *ctx, mxe_mat m, int32_t k, int32_t variant) 
 
 // ---- batches ------------------------------------------------------------------------
 
+// Deals the matrices to the per-XCD queues: largest first (bytes one product
+// moves) onto the least loaded queue, so each XCD's share is balanced and its
+// matrices' x stays in its own L2. Each queue lists its matrices in item
+// order, with tile_begin counted within the queue.
+static void assign_queues(std::vector<BatchDesc> &descs, const std::vector<uint64_t> &cost,
+                          std::vector<int32_t> &qent, BatchQueues &qs) {
+    const int32_t n = (int32_t)descs.size();
+    std::vector<int32_t> order(n), queue_of(n);
+    for (int32_t i = 0; i < n; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int32_t a, int32_t b) { return cost[a] > cost[b]; });
+    uint64_t load[kBatchQueues] = {};
+    for (int32_t i : order) {
+        const int q = (int)(std::min_element(load, load + kBatchQueues) - load);
+        queue_of[i] = q;
+        load[q] += cost[i];
+    }
+    qent.clear();
+    for (int q = 0; q < kBatchQueues; ++q) {
+        qs.qbegin[q] = (int32_t)qent.size();
+        int64_t tiles = 0;
+        for (int32_t i = 0; i < n; ++i) {
+            if (queue_of[i] != q) continue;
+            descs[i].tile_begin = (int32_t)tiles;
+            tiles += (descs[i].nrows + descs[i].rows_per_tile - 1) / descs[i].rows_per_tile;
+            qent.push_back(i);
+        }
+        qs.qtiles[q] = (int32_t)tiles;
+    }
+    qs.qbegin[kBatchQueues] = (int32_t)qent.size();
+}
+
 static mxe_status build_descs(mxe_ctx *ctx, int32_t count, const mxe_item *items, hipStream_t s,
-                              std::vector<BatchDesc> &descs, int32_t &total_tiles) {
+                              std::vector<BatchDesc> &descs, std::vector<int32_t> &qent,
+                              BatchQueues &qs) {
     if (count < 1 || !items) return fail(MXE_ERR_INVALID_ARG, "empty batch");
     descs.clear();
+    std::vector<uint64_t> cost;
     int64_t tiles = 0;
     for (int32_t i = 0; i < count; ++i) {
         const mxe_item &it = items[i];
@@ -939,12 +973,12 @@ static mxe_status build_descs(mxe_ctx *ctx, int32_t count, const mxe_item *items
         d.kclass = kclass_of(it.k);
         d.lanes = std::max(r.group_lanes, d.kclass);   // set_variant may force fewer
         d.rows_per_tile = (256 / r.group_lanes) * 4;
-        d.tile_begin = (int32_t)tiles;
         tiles += (A->nrows + d.rows_per_tile - 1) / d.rows_per_tile;
         if (tiles > INT32_MAX) return fail(MXE_ERR_UNSUPPORTED, "too many tiles in batch");
         descs.push_back(d);
+        cost.push_back(request_bytes(*A, it.k));
     }
-    total_tiles = (int32_t)tiles;
+    assign_queues(descs, cost, qent, qs);
     return MXE_OK;
 }
 
@@ -961,16 +995,20 @@ mxe_status mxe_spmv_batch(mxe_ctx *ctx, int32_t count, const mxe_item *items, vo
     DeviceGuard g(ctx->device);
     hipStream_t s = (hipStream_t)stream;
     std::vector<BatchDesc> descs;
-    int32_t total = 0;
-    mxe_status st = build_descs(ctx, count, items, s, descs, total);
+    std::vector<int32_t> qent;
+    BatchQueues qs{};
+    mxe_status st = build_descs(ctx, count, items, s, descs, qent, qs);
     if (st) return st;
     Scratch dd, ctr;
     if ((st = dd.alloc(sizeof(BatchDesc) * descs.size(), s))) return st;
-    if ((st = ctr.alloc(sizeof(int32_t), s))) return st;
-    MXE_HIP(hipStreamSynchronize(s));     // pool blocks ready before the blocking copy
+    if ((st = ctr.alloc(sizeof(int32_t) * (kBatchQueues + qent.size()), s))) return st;
+    int32_t *counters = (int32_t *)ctr.p;
+    MXE_HIP(hipStreamSynchronize(s));     // pool blocks ready before the blocking copies
     MXE_HIP(hipMemcpy(dd.p, descs.data(), sizeof(BatchDesc) * descs.size(), hipMemcpyHostToDevice));
-    MXE_HIP(launch_batch_reset((int32_t *)ctr.p, s));
-    MXE_HIP(launch_spmv_batch((const BatchDesc *)dd.p, count, total, (int32_t *)ctr.p,
+    MXE_HIP(hipMemcpy(counters + kBatchQueues, qent.data(), sizeof(int32_t) * qent.size(),
+                      hipMemcpyHostToDevice));
+    MXE_HIP(launch_batch_reset(counters, s));
+    MXE_HIP(launch_spmv_batch((const BatchDesc *)dd.p, counters + kBatchQueues, qs, counters,
                               batch_grid_size(), common_vtype(descs), s));
     return MXE_OK;
 }
@@ -980,26 +1018,28 @@ mxe_status mxe_batch_create(mxe_ctx *ctx, int32_t count, const mxe_item *items, 
     std::lock_guard<std::recursive_mutex> lk(ctx->mu);
     DeviceGuard g(ctx->device);
     auto plan = std::make_unique<Plan>();
-    mxe_status st = build_descs(ctx, count, items, nullptr, plan->descs, plan->total_tiles);
+    mxe_status st = build_descs(ctx, count, items, nullptr, plan->descs, plan->qent, plan->queues);
     if (st) return st;
     plan->items.assign(items, items + count);
     MXE_HIP(hipMalloc(&plan->descs_dev, sizeof(BatchDesc) * plan->descs.size()));
-    MXE_HIP(hipMalloc(&plan->counter, sizeof(int32_t)));
+    MXE_HIP(hipMalloc(&plan->counters, sizeof(int32_t) * (kBatchQueues + plan->qent.size())));
     MXE_HIP(hipMemcpy(plan->descs_dev, plan->descs.data(), sizeof(BatchDesc) * plan->descs.size(),
                       hipMemcpyHostToDevice));
+    MXE_HIP(hipMemcpy(plan->counters + kBatchQueues, plan->qent.data(),
+                      sizeof(int32_t) * plan->qent.size(), hipMemcpyHostToDevice));
     MXE_HIP(hipStreamCreateWithFlags(&plan->capture_stream, hipStreamNonBlocking));
     hipStream_t cs = plan->capture_stream;
     MXE_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-    hipError_t e1 = launch_batch_reset(plan->counter, cs);
-    hipError_t e2 = launch_spmv_batch(plan->descs_dev, count, plan->total_tiles, plan->counter,
-                                      batch_grid_size(), common_vtype(plan->descs), cs);
+    hipError_t e1 = launch_batch_reset(plan->counters, cs);
+    hipError_t e2 = launch_spmv_batch(plan->descs_dev, plan->counters + kBatchQueues, plan->queues,
+                                      plan->counters, batch_grid_size(), common_vtype(plan->descs), cs);
     hipError_t e3 = hipStreamEndCapture(cs, &plan->graph);
     if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) {
         Plan &p = *plan;
         if (p.graph) (void)hipGraphDestroy(p.graph);
         (void)hipStreamDestroy(p.capture_stream);
         (void)hipFree(p.descs_dev);
-        (void)hipFree(p.counter);
+        (void)hipFree(p.counters);
         return hip_fail(e1 != hipSuccess ? e1 : e2 != hipSuccess ? e2 : e3, "batch graph capture");
     }
     MXE_HIP(hipGraphInstantiate(&plan->exec, plan->graph, nullptr, nullptr, 0));
@@ -1063,7 +1103,7 @@ mxe_status mxe_batch_destroy(mxe_ctx *ctx, mxe_plan h) {
     if (p.graph) (void)hipGraphDestroy(p.graph);
     if (p.capture_stream) (void)hipStreamDestroy(p.capture_stream);
     (void)hipFree(p.descs_dev);
-    (void)hipFree(p.counter);
+    (void)hipFree(p.counters);
     ctx->plans.erase(it);
     return MXE_OK;
 }

@@ -161,14 +161,22 @@ struct BatchDesc {             // one matrix of a batch (device-resident table)
     int32_t vtype, lanes;      // lanes per row (1..64), >= kclass
     int32_t kclass;            // k rounded up to a power of two (column lanes)
     int32_t rows_per_tile;     // rows one work item covers
-    int32_t tile_begin;        // first global tile index of this matrix
+    int32_t tile_begin;        // first tile index of this matrix within its queue
 };
-// descs: device table of count entries; counter: device int32 zeroed by
-// launch_batch_reset before each launch. total_tiles = sum of tiles.
-hipError_t launch_batch_reset(int32_t *counter, hipStream_t s);
+// One work queue per XCD: queue q holds the matrices qent[qbegin[q] ..
+// qbegin[q+1]) (indices into the desc table, in tile order) and qtiles[q]
+// tiles in all.
+constexpr int kBatchQueues = 8;
+struct BatchQueues {
+    int32_t qbegin[kBatchQueues + 1];
+    int32_t qtiles[kBatchQueues];
+};
+// counters: kBatchQueues device ints zeroed by launch_batch_reset before each
+// launch.
+hipError_t launch_batch_reset(int32_t *counters, hipStream_t s);
 // vtype: the ValType every item shares, or -1 for a mixed batch.
-hipError_t launch_spmv_batch(const BatchDesc *descs, int32_t count, int32_t total_tiles,
-                             int32_t *counter, int32_t grid, int vtype, hipStream_t s);
+hipError_t launch_spmv_batch(const BatchDesc *descs, const int32_t *qent, const BatchQueues &queues,
+                             int32_t *counters, int32_t grid, int vtype, hipStream_t s);
 int32_t batch_grid_size();
 
 // ---- serving: pack / unpack merged right-hand sides -------------------------

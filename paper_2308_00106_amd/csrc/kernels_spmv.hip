@@ -552,29 +552,37 @@ hipError_t coo_launch(const SpmvArgs &a, hipStream_t s) {
     return hipGetLastError();
 }
 
-// Persistent grid: each workgroup takes the next tile index from a device
-// counter until all tiles of all matrices are done; every workgroup reaches
-// the exit test, so the grid always drains. VT is the value type shared by
-// every item, or -1 for a batch that mixes them (that instance carries every
-// path and so more registers).
+// Persistent grid with one work queue per XCD (workgroups are dealt to the
+// 8 XCDs round-robin): a workgroup takes tiles from its own XCD's queue, whose
+// matrices' x then stays in that XCD's L2, and when it is empty from the
+// other queues in turn. Every pull either returns a tile or finds a queue
+// exhausted, and each workgroup stops after finding all of them exhausted, so
+// the grid always drains. VT is the value type shared by every item, or -1 for
+// a batch that mixes them (that instance carries every path and so more
+// registers).
 template <int VT>
 __global__ __launch_bounds__(kBlock) void k_spmv_batch(const BatchDesc *__restrict__ descs,
-                                                       int32_t count, int32_t total_tiles,
-                                                       int32_t *counter) {
+                                                       const int32_t *__restrict__ qent,
+                                                       BatchQueues qs, int32_t *counters) {
     __shared__ int32_t tile_s;
-    for (;;) {
-        if (threadIdx.x == 0) tile_s = atomicAdd(counter, 1);
+    const int home = blockIdx.x % kBatchQueues;
+    for (int step = 0; step < kBatchQueues;) {
+        const int q = (home + step) % kBatchQueues;
+        if (threadIdx.x == 0) tile_s = atomicAdd(&counters[q], 1);
         __syncthreads();
         const int32_t tile = tile_s;
         __syncthreads();
-        if (tile >= total_tiles) break;
-        int32_t lo = 0, hi = count - 1;               // last desc with tile_begin <= tile
+        if (tile >= qs.qtiles[q]) {                   // queue exhausted: next one
+            ++step;
+            continue;
+        }
+        int32_t lo = qs.qbegin[q], hi = qs.qbegin[q + 1] - 1;   // last matrix starting <= tile
         while (lo < hi) {
-            int32_t mid = (lo + hi + 1) >> 1;
-            if (descs[mid].tile_begin <= tile) lo = mid;
+            const int32_t mid = (lo + hi + 1) >> 1;
+            if (descs[qent[mid]].tile_begin <= tile) lo = mid;
             else hi = mid - 1;
         }
-        const BatchDesc d = descs[lo];
+        const BatchDesc d = descs[qent[lo]];
         const int32_t r0 = (tile - d.tile_begin) * d.rows_per_tile;
         const int32_t r1 = min(d.nrows, r0 + d.rows_per_tile);
         if constexpr (VT == VAL_F64) {
@@ -591,7 +599,9 @@ __global__ __launch_bounds__(kBlock) void k_spmv_batch(const BatchDesc *__restri
     }
 }
 
-__global__ void k_batch_reset(int32_t *counter) { *counter = 0; }
+__global__ void k_batch_reset(int32_t *counters) {
+    if (threadIdx.x < kBatchQueues) counters[threadIdx.x] = 0;
+}
 
 // ---- launch helpers ---------------------------------------------------------------------
 
@@ -708,32 +718,32 @@ hipError_t launch_spmv(const SpmvArgs &a, int variant, hipStream_t s) {
     }
 }
 
-hipError_t launch_batch_reset(int32_t *counter, hipStream_t s) {
-    hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(1), 0, s, counter);
+hipError_t launch_batch_reset(int32_t *counters, hipStream_t s) {
+    hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(kWave), 0, s, counters);
     return hipGetLastError();
 }
 
 int32_t batch_grid_size() { return 256 * 8; }   // 8 resident workgroups per CU
 
-hipError_t launch_spmv_batch(const BatchDesc *descs, int32_t count, int32_t total_tiles,
-                             int32_t *counter, int32_t grid, int vtype, hipStream_t s) {
-    if (count <= 0 || total_tiles <= 0) return hipSuccess;
+hipError_t launch_spmv_batch(const BatchDesc *descs, const int32_t *qent, const BatchQueues &qs,
+                             int32_t *counters, int32_t grid, int vtype, hipStream_t s) {
+    if (qs.qbegin[kBatchQueues] <= 0) return hipSuccess;
     switch (vtype) {
     case VAL_F64:
-        hipLaunchKernelGGL(k_spmv_batch<VAL_F64>, dim3(grid), dim3(kBlock), 0, s, descs, count,
-                           total_tiles, counter);
+        hipLaunchKernelGGL(k_spmv_batch<VAL_F64>, dim3(grid), dim3(kBlock), 0, s, descs, qent, qs,
+                           counters);
         break;
     case VAL_F32:
-        hipLaunchKernelGGL(k_spmv_batch<VAL_F32>, dim3(grid), dim3(kBlock), 0, s, descs, count,
-                           total_tiles, counter);
+        hipLaunchKernelGGL(k_spmv_batch<VAL_F32>, dim3(grid), dim3(kBlock), 0, s, descs, qent, qs,
+                           counters);
         break;
     case VAL_BF16:
-        hipLaunchKernelGGL(k_spmv_batch<VAL_BF16>, dim3(grid), dim3(kBlock), 0, s, descs, count,
-                           total_tiles, counter);
+        hipLaunchKernelGGL(k_spmv_batch<VAL_BF16>, dim3(grid), dim3(kBlock), 0, s, descs, qent, qs,
+                           counters);
         break;
     default:
-        hipLaunchKernelGGL(k_spmv_batch<-1>, dim3(grid), dim3(kBlock), 0, s, descs, count,
-                           total_tiles, counter);
+        hipLaunchKernelGGL(k_spmv_batch<-1>, dim3(grid), dim3(kBlock), 0, s, descs, qent, qs,
+                           counters);
     }
     return hipGetLastError();
 }

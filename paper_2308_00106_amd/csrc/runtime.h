@@ -80,8 +80,9 @@ struct Plan {
     std::vector<mxe_item> items;
     std::vector<BatchDesc> descs;
     BatchDesc *descs_dev = nullptr;
-    int32_t *counter = nullptr;
-    int32_t total_tiles = 0;
+    std::vector<int32_t> qent;          // per-XCD queue entries (desc indices)
+    BatchQueues queues{};
+    int32_t *counters = nullptr;        // device: kBatchQueues counters, then qent
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     hipStream_t capture_stream = nullptr;
