@@ -196,6 +196,127 @@ __global__ __launch_bounds__(kBlock) void k_bucket_rank(int64_t nbuckets, uint64
     }
 }
 
+// LDS radix path (n up to kLdsPermMax): keys are bucketed by their top
+// `bits` bits with per-workgroup LDS histograms (no device-wide atomics), then
+// one workgroup per bucket splits it by the next kSubBits bits in LDS and
+// ranks every item by (key, index) inside its sub-bucket, a handful of items.
+constexpr int kPermItems = 8192;                         // indices per bucketing workgroup
+constexpr int kPermMaxBits = 12;                         // at most 4096 buckets
+constexpr int kPermMeanBucket = 2048;
+constexpr int kBucketCap = 4096;                         // items a workgroup sorts in LDS
+constexpr int kSubBits = 8;                              // sub-buckets = kBlock
+constexpr int64_t kLdsPermMax = (int64_t)kPermMeanBucket << kPermMaxBits;
+
+inline int radix_bits(int64_t n) {                       // mean bucket <= kPermMeanBucket
+    int b = 0;
+    while (b < kPermMaxBits && (n >> b) > kPermMeanBucket) ++b;
+    return b;
+}
+
+__device__ inline uint32_t top_digit(uint64_t key, int bits) {
+    return bits == 0 ? 0u : (uint32_t)(key >> (64 - bits));
+}
+__device__ inline uint32_t sub_digit(uint64_t key, int bits) {
+    return (uint32_t)(key >> (64 - bits - kSubBits)) & ((1u << kSubBits) - 1u);
+}
+
+// counts[d * nwg + w] = items of workgroup w's index range in bucket d
+__global__ __launch_bounds__(kBlock) void k_perm_count(int64_t n, uint64_t seed, int bits,
+                                                       int32_t nwg, int32_t *counts) {
+    extern __shared__ int32_t hist[];
+    const int nd = 1 << bits;
+    for (int d = threadIdx.x; d < nd; d += kBlock) hist[d] = 0;
+    __syncthreads();
+    const int64_t i0 = (int64_t)blockIdx.x * kPermItems;
+    const int64_t i1 = i0 + kPermItems < n ? i0 + kPermItems : n;
+    for (int64_t i = i0 + threadIdx.x; i < i1; i += kBlock)
+        atomicAdd(&hist[top_digit(sm64_key(seed, (uint64_t)i), bits)], 1);
+    __syncthreads();
+    for (int d = threadIdx.x; d < nd; d += kBlock) counts[(int64_t)d * nwg + blockIdx.x] = hist[d];
+}
+
+// offsets: the exclusive scan of counts; items[pos] = index, in any order
+// inside a bucket (the bucket sort fixes the order)
+__global__ __launch_bounds__(kBlock) void k_perm_scatter(int64_t n, uint64_t seed, int bits,
+                                                         int32_t nwg, const int32_t *offsets,
+                                                         int32_t *items) {
+    extern __shared__ int32_t cursor[];
+    const int nd = 1 << bits;
+    for (int d = threadIdx.x; d < nd; d += kBlock) cursor[d] = offsets[(int64_t)d * nwg + blockIdx.x];
+    __syncthreads();
+    const int64_t i0 = (int64_t)blockIdx.x * kPermItems;
+    const int64_t i1 = i0 + kPermItems < n ? i0 + kPermItems : n;
+    for (int64_t i = i0 + threadIdx.x; i < i1; i += kBlock) {
+        const int32_t pos = atomicAdd(&cursor[top_digit(sm64_key(seed, (uint64_t)i), bits)], 1);
+        items[pos] = (int32_t)i;
+    }
+}
+
+__device__ inline bool key_less(uint64_t ka, int32_t ia, uint64_t kb, int32_t ib) {
+    return ka < kb || (ka == kb && ia < ib);
+}
+
+// One workgroup per bucket: final position of each item = bucket start +
+// start of its sub-bucket + its rank by (key, index) inside the sub-bucket.
+// A bucket above kBucketCap (not expected from uniform keys) is ranked
+// against the whole bucket in memory instead.
+__global__ __launch_bounds__(kBlock) void k_perm_bucket_sort(int32_t nd, int32_t nwg, uint64_t seed,
+                                                             int bits, const int32_t *offsets,
+                                                             const int32_t *items, int32_t *perm,
+                                                             int32_t *inv) {
+    __shared__ uint64_t skey[kBucketCap];
+    __shared__ int32_t sidx[kBucketCap];
+    __shared__ int32_t sub[kBlock + 1];
+    __shared__ int32_t cursor[kBlock];
+    __shared__ int32_t wsum[kBlock / kWave];
+    const int32_t d = blockIdx.x;
+    const int32_t o = offsets[(int64_t)d * nwg];
+    const int32_t m = offsets[(int64_t)(d + 1) * nwg] - o;   // the scan's last entry is n
+    if (m > kBucketCap) {
+        for (int32_t t = threadIdx.x; t < m; t += kBlock) {
+            const int32_t idx = items[o + t];
+            const uint64_t key = sm64_key(seed, (uint64_t)idx);
+            int32_t r = 0;
+            for (int32_t u = 0; u < m; ++u) {
+                const int32_t iu = items[o + u];
+                r += key_less(sm64_key(seed, (uint64_t)iu), iu, key, idx);
+            }
+            perm[o + r] = idx;
+            if (inv) inv[idx] = o + r;
+        }
+        return;
+    }
+    sub[threadIdx.x] = 0;
+    __syncthreads();
+    for (int32_t t = threadIdx.x; t < m; t += kBlock)
+        atomicAdd(&sub[sub_digit(sm64_key(seed, (uint64_t)items[o + t]), bits)], 1);
+    __syncthreads();
+    int32_t total;
+    const int32_t ex = block_exclusive_scan(sub[threadIdx.x], wsum, &total);
+    sub[threadIdx.x] = ex;
+    cursor[threadIdx.x] = ex;
+    if (threadIdx.x == 0) sub[kBlock] = total;
+    __syncthreads();
+    for (int32_t t = threadIdx.x; t < m; t += kBlock) {
+        const int32_t idx = items[o + t];
+        const uint64_t key = sm64_key(seed, (uint64_t)idx);
+        const int32_t p = atomicAdd(&cursor[sub_digit(key, bits)], 1);
+        skey[p] = key;
+        sidx[p] = idx;
+    }
+    __syncthreads();
+    for (int32_t p = threadIdx.x; p < m; p += kBlock) {
+        const uint64_t key = skey[p];
+        const int32_t idx = sidx[p];
+        const uint32_t sd = sub_digit(key, bits);
+        const int32_t b0 = sub[sd], b1 = sub[sd + 1];
+        int32_t r = 0;
+        for (int32_t q = b0; q < b1; ++q) r += key_less(skey[q], sidx[q], key, idx);
+        perm[o + b0 + r] = idx;
+        if (inv) inv[idx] = o + b0 + r;
+    }
+}
+
 // ---- permuted CSR --------------------------------------------------------------
 
 __global__ __launch_bounds__(kBlock) void k_perm_row_len(int32_t nrows, const int32_t *rp,
@@ -499,6 +620,12 @@ hipError_t launch_exclusive_scan(const int32_t *in, int32_t *out, int64_t n, voi
 }
 
 size_t random_perm_ws_bytes(int64_t n) {
+    if (n <= kLdsPermMax) {
+        const int64_t nwg = std::max<int64_t>(1, cdiv(n, kPermItems));
+        const int64_t ncounts = (nwg << radix_bits(n)) + 1;
+        return align256(sizeof(int32_t) * ncounts) + align256(sizeof(int32_t) * (n + 1)) +
+               scan_ws_bytes(ncounts);
+    }
     int64_t nb = int64_t(1) << bucket_bits(n);
     return align256(sizeof(int32_t) * (nb + 1)) + 2 * align256(sizeof(int32_t) * (n + 1)) +
            scan_ws_bytes(nb + 1);
@@ -507,6 +634,27 @@ size_t random_perm_ws_bytes(int64_t n) {
 hipError_t launch_random_perm(int64_t n, uint64_t stream_seed, int32_t *perm, int32_t *inv,
                               void *ws, hipStream_t s) {
     if (n <= 0) return hipSuccess;
+    if (n <= kLdsPermMax) {
+        const int bits = radix_bits(n);
+        const int32_t nd = 1 << bits;
+        const int32_t nwg = (int32_t)std::max<int64_t>(1, cdiv(n, kPermItems));
+        const int64_t ncounts = (int64_t)nwg * nd + 1;
+        char *w = (char *)ws;
+        int32_t *counts = (int32_t *)w;  w += align256(sizeof(int32_t) * ncounts);
+        int32_t *items = (int32_t *)w;   w += align256(sizeof(int32_t) * (n + 1));
+        void *scan_ws = w;
+        const size_t lds = sizeof(int32_t) * (size_t)nd;
+        hipLaunchKernelGGL(k_perm_count, dim3(nwg), dim3(kBlock), lds, s, n, stream_seed, bits, nwg,
+                           counts);
+        hipError_t e = launch_fill_i32(counts + ncounts - 1, 1, 0, s);
+        if (e != hipSuccess) return e;
+        if ((e = launch_exclusive_scan(counts, counts, ncounts, scan_ws, s)) != hipSuccess) return e;
+        hipLaunchKernelGGL(k_perm_scatter, dim3(nwg), dim3(kBlock), lds, s, n, stream_seed, bits, nwg,
+                           (const int32_t *)counts, items);
+        hipLaunchKernelGGL(k_perm_bucket_sort, dim3(nd), dim3(kBlock), 0, s, nd, nwg, stream_seed,
+                           bits, (const int32_t *)counts, (const int32_t *)items, perm, inv);
+        return hipGetLastError();
+    }
     const int bits = bucket_bits(n);
     const int64_t nb = int64_t(1) << bits;
     char *w = (char *)ws;

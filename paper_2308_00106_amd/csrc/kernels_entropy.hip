@@ -25,8 +25,9 @@ namespace mxe {
 namespace {
 
 constexpr int kBlock = 256;
-constexpr int kHistLds = 16384;                 // block-columns held in LDS (64 KB)
-constexpr int64_t kHistSplitItems = 65536;      // entries per workgroup before splitting
+constexpr int kHistLds = 16384;                 // block-columns held in LDS (at most 64 KB)
+constexpr int64_t kHistSplitItems = 16384;      // entries per workgroup before splitting
+constexpr int64_t kHistMinGroups = 2048;        // workgroups enough to fill the chip
 constexpr int kEntGrid = 1024;                  // fixed grid: fixed reduction order
 
 inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
@@ -43,7 +44,7 @@ __global__ __launch_bounds__(kBlock) void k_block_hist(int32_t nrows, int32_t nc
                                                        const int32_t *__restrict__ col,
                                                        int32_t grid_r, int32_t grid_c,
                                                        double inv_n, uint32_t *__restrict__ hist) {
-    __shared__ uint32_t bins[kHistLds];
+    extern __shared__ uint32_t bins[];                  // grid_c counters when they fit
     const int64_t bi = blockIdx.x;
     const int split = gridDim.y, part = blockIdx.y;
     const int64_t r0 = (bi * nrows + grid_r - 1) / grid_r;
@@ -283,7 +284,7 @@ hipError_t launch_block_hist(int32_t nrows, int32_t ncols, int64_t nnz, const in
                              const int32_t *col, int32_t grid_r, int32_t grid_c, uint32_t *hist,
                              hipStream_t s) {
     const int64_t bins = (int64_t)grid_r * grid_c;
-    int64_t split = cdiv(cdiv(nnz, grid_r), kHistSplitItems);
+    int64_t split = std::max(cdiv(cdiv(nnz, grid_r), kHistSplitItems), cdiv(kHistMinGroups, grid_r));
     if (split < 1) split = 1;
     if (split > 65535) split = 65535;
     const bool needs_zero = split > 1 || grid_c > kHistLds;
@@ -292,7 +293,8 @@ hipError_t launch_block_hist(int32_t nrows, int32_t ncols, int64_t nnz, const in
         hipLaunchKernelGGL(k_zero_u32, dim3(g), dim3(kBlock), 0, s, hist, bins);
     }
     const double inv_n = 1.0 / (double)ncols;
-    hipLaunchKernelGGL(k_block_hist, dim3(grid_r, (unsigned)split), dim3(kBlock), 0, s, nrows,
+    const size_t lds = grid_c <= kHistLds ? sizeof(uint32_t) * (size_t)grid_c : 0;
+    hipLaunchKernelGGL(k_block_hist, dim3(grid_r, (unsigned)split), dim3(kBlock), lds, s, nrows,
                        ncols, rp, col, grid_r, grid_c, inv_n, hist);
     return hipGetLastError();
 }

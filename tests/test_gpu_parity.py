@@ -49,6 +49,18 @@ def test_permutation_matches_oracle(ctx, n):
     ctx.release(A)
 
 
+@pytest.mark.slow
+def test_permutation_large_n_bucket_path(ctx):
+    """Above 2048 << 12 indices the permutation takes its global bucket path."""
+    n = 9_000_000
+    A = ctx.register(_diag(n, 7))
+    B = ctx.permute(A, 5, mx.ROWS)
+    rp, _ = ctx.get_permutation(B)
+    assert np.array_equal(rp, oracle.permutation(n, oracle.stream_seeds(5)[0]))
+    ctx.release(B)
+    ctx.release(A)
+
+
 def test_permute_modes_identity_parts(ctx):
     A0 = synth.random_csr(300, 200, 0.05, 1)
     A = ctx.register(A0)
