@@ -33,6 +33,7 @@ namespace {
 constexpr int kSlabBlock = 1024;                    // 16 wavefronts
 constexpr int kSubBlocks = kSlabBlock / kWave;      // wavefront sub-blocks per block
 constexpr int kSlabMax = 64;                       // column slabs per layout
+constexpr int kFillBatch = 4;                      // 64-entry chunks loaded together by the build
 // 64-entry chunks each wavefront keeps in flight (fewer for wide right-hand sides)
 template <int KM> struct Unroll { static constexpr int value = KM <= 2 ? 4 : KM <= 4 ? 2 : 1; };
 
@@ -65,8 +66,14 @@ __global__ __launch_bounds__(kSlabBlock) void k_slab_count(SlabGeom g, const int
     if (r0 < r1) {
         const double inv_w = 1.0 / g.width;
         const int32_t e1 = rp[r1];
-        for (int32_t e = rp[r0] + lane; e < e1; e += kWave)
-            atomicAdd(&c[wave][slab_of(col[e], g.width, inv_w)], 1);
+        for (int32_t e = rp[r0] + lane; e < e1; e += kFillBatch * kWave) {
+            int32_t cv[kFillBatch];                             // loads of the batch first
+#pragma unroll
+            for (int j = 0; j < kFillBatch; ++j) cv[j] = e + j * kWave < e1 ? col[e + j * kWave] : -1;
+#pragma unroll
+            for (int j = 0; j < kFillBatch; ++j)
+                if (cv[j] >= 0) atomicAdd(&c[wave][slab_of(cv[j], g.width, inv_w)], 1);
+        }
     }
     __syncthreads();
     int32_t *out = cnt + ((int64_t)blockIdx.x * kSubBlocks + wave) * g.slabs;
@@ -101,39 +108,49 @@ __global__ __launch_bounds__(kSlabBlock) void k_slab_fill(SlabGeom g, const int3
     const double inv_w = 1.0 / g.width;
     const int32_t e0 = wrp[0], e1 = wrp[nr];
     const uint64_t below = (uint64_t(1) << lane) - 1;
-    for (int32_t c0 = e0; c0 < e1; c0 += kWave) {           // uniform per wavefront
-        const int32_t e = c0 + lane;
-        const bool valid = e < e1;
-        int32_t sl = 0, rloc = 0, cv = 0;
-        V v{};
-        if (valid) {
-            cv = col[e];
-            v = val[e];
-            sl = slab_of(cv, g.width, inv_w);
-            int32_t lo = 0, hi = nr - 1;                    // last row with wrp[row] <= e
-            while (lo < hi) {
-                const int32_t mid = (lo + hi + 1) >> 1;
-                if (wrp[mid] <= e) lo = mid;
-                else hi = mid - 1;
-            }
-            rloc = lo;
-        }
-        uint64_t same = __ballot(valid);
+    for (int32_t b0 = e0; b0 < e1; b0 += kFillBatch * kWave) {    // uniform per wavefront
+        int32_t cvs[kFillBatch];                                 // the batch's loads first
+        V vs[kFillBatch];
 #pragma unroll
-        for (int b = 0; b < 6; ++b) {
-            const uint64_t m = __ballot(valid && ((sl >> b) & 1));
-            same &= ((sl >> b) & 1) ? m : ~m;
+        for (int j = 0; j < kFillBatch; ++j) {
+            const int32_t e = b0 + j * kWave + lane;
+            cvs[j] = e < e1 ? col[e] : 0;
+            vs[j] = e < e1 ? val[e] : V{};
         }
-        if (valid) {
-            const int32_t pos = base[wave][sl] + __popcll(same & below);
-            idx_out[pos] = ((uint32_t)rloc << g.cbits) | (uint32_t)cv;
-            val_out[pos] = v;
+#pragma unroll
+        for (int j = 0; j < kFillBatch; ++j) {
+            const int32_t c0 = b0 + j * kWave;
+            if (c0 >= e1) break;                                 // uniform per wavefront
+            const int32_t e = c0 + lane;
+            const bool valid = e < e1;
+            int32_t sl = 0, rloc = 0;
+            if (valid) {
+                sl = slab_of(cvs[j], g.width, inv_w);
+                int32_t lo = 0, hi = nr - 1;                     // last row with wrp[row] <= e
+                while (lo < hi) {
+                    const int32_t mid = (lo + hi + 1) >> 1;
+                    if (wrp[mid] <= e) lo = mid;
+                    else hi = mid - 1;
+                }
+                rloc = lo;
+            }
+            uint64_t same = __ballot(valid);
+#pragma unroll
+            for (int b = 0; b < 6; ++b) {
+                const uint64_t m = __ballot(valid && ((sl >> b) & 1));
+                same &= ((sl >> b) & 1) ? m : ~m;
+            }
+            if (valid) {
+                const int32_t pos = base[wave][sl] + __popcll(same & below);
+                idx_out[pos] = ((uint32_t)rloc << g.cbits) | (uint32_t)cvs[j];
+                val_out[pos] = vs[j];
+            }
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            if (valid && (same & below) == 0) base[wave][sl] += __popcll(same);
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            __builtin_amdgcn_wave_barrier();
         }
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        if (valid && (same & below) == 0) base[wave][sl] += __popcll(same);
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        __builtin_amdgcn_wave_barrier();
     }
 }
 
