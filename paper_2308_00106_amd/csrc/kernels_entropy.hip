@@ -134,13 +134,22 @@ __device__ inline void block_reduce(dd &acc, unsigned long long &s, unsigned lon
     nz = sz[0];
 }
 
-__global__ __launch_bounds__(kBlock) void k_entropy_partial(const uint32_t *__restrict__ hist,
-                                                            int64_t bins, EntPartial *part) {
+// Count of counts: cc[c] = number of bins holding exactly c entries, for
+// c < kCountDirect (LDS per workgroup, then exact integer atomics into one
+// table); bins with more entries add c ln c to the workgroup's partial
+// directly. S and the nonzero-bin count are summed alongside.
+constexpr int kCountDirect = 4096;
+
+__global__ __launch_bounds__(kBlock) void k_entropy_counts(const uint32_t *__restrict__ hist,
+                                                           int64_t bins, uint32_t *__restrict__ cc,
+                                                           EntPartial *part) {
+    __shared__ uint32_t lcc[kCountDirect];
     __shared__ dd coef[kLnTerms];
     __shared__ dd ln2;
     __shared__ dd sh[kBlock];
     __shared__ unsigned long long ss[kBlock], sz[kBlock];
-    setup_log_tables(coef, &ln2);
+    for (int c = threadIdx.x; c < kCountDirect; c += kBlock) lcc[c] = 0;
+    setup_log_tables(coef, &ln2);                         // synchronizes
     dd acc{0.0, 0.0};
     unsigned long long s = 0, nz = 0;
     for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < bins;
@@ -148,11 +157,16 @@ __global__ __launch_bounds__(kBlock) void k_entropy_partial(const uint32_t *__re
         const uint32_t h = hist[i];
         s += h;
         nz += h != 0;
-        if (h >= 2) {
+        if (h < kCountDirect) {
+            if (h >= 2) atomicAdd(&lcc[h], 1u);
+        } else {
             const double hd = (double)h;
             acc = dd_add(acc, dd_mul_d(dd_ln_int(hd, ln2, coef), hd));
         }
     }
+    __syncthreads();
+    for (int c = threadIdx.x; c < kCountDirect; c += kBlock)
+        if (lcc[c]) atomicAdd(&cc[c], lcc[c]);
     block_reduce(acc, s, nz, sh, ss, sz);
     if (threadIdx.x == 0) part[blockIdx.x] = EntPartial{acc.hi, acc.lo, s, nz};
 }
@@ -193,7 +207,10 @@ __device__ inline void entropy_finish(dd acc, unsigned long long s, unsigned lon
     result[3] = sd;
 }
 
-__global__ __launch_bounds__(kBlock) void k_entropy_final(const EntPartial *part, int nparts,
+// T = sum over c of cc[c] c ln c (c in fixed order per thread, then a fixed
+// tree) plus the large-count partials in workgroup order.
+__global__ __launch_bounds__(kBlock) void k_entropy_final(const uint32_t *__restrict__ cc,
+                                                          const EntPartial *part, int nparts,
                                                           double *result) {
     __shared__ dd coef[kLnTerms];
     __shared__ dd ln2;
@@ -202,6 +219,11 @@ __global__ __launch_bounds__(kBlock) void k_entropy_final(const EntPartial *part
     setup_log_tables(coef, &ln2);
     dd acc{0.0, 0.0};
     unsigned long long s = 0, nz = 0;
+    for (int c = 2 + threadIdx.x; c < kCountDirect; c += kBlock) {
+        if (cc[c] == 0) continue;
+        const double cd = (double)c;
+        acc = dd_add(acc, dd_mul_d(dd_mul_d(dd_ln_int(cd, ln2, coef), cd), (double)cc[c]));
+    }
     for (int i = threadIdx.x; i < nparts; i += kBlock) {
         acc = dd_add(acc, dd{part[i].hi, part[i].lo});
         s += part[i].s;
@@ -299,15 +321,20 @@ hipError_t launch_block_hist(int32_t nrows, int32_t ncols, int64_t nnz, const in
     return hipGetLastError();
 }
 
-size_t entropy_ws_bytes(int64_t) { return sizeof(EntPartial) * kEntGrid + 256; }
+size_t entropy_ws_bytes(int64_t) {
+    return sizeof(uint32_t) * kCountDirect + sizeof(EntPartial) * kEntGrid + 256;
+}
 
 hipError_t launch_entropy(const uint32_t *hist, int64_t bins, double *result, void *ws,
                           hipStream_t s) {
-    EntPartial *part = (EntPartial *)ws;
+    uint32_t *cc = (uint32_t *)ws;
+    EntPartial *part = (EntPartial *)(cc + kCountDirect);
+    hipLaunchKernelGGL(k_zero_u32, dim3(kCountDirect / kBlock), dim3(kBlock), 0, s, cc,
+                       (int64_t)kCountDirect);
     int g = (int)std::min<int64_t>(kEntGrid, std::max<int64_t>(1, cdiv(bins, kBlock)));
-    hipLaunchKernelGGL(k_entropy_partial, dim3(g), dim3(kBlock), 0, s, hist, bins, part);
-    hipLaunchKernelGGL(k_entropy_final, dim3(1), dim3(kBlock), 0, s, (const EntPartial *)part, g,
-                       result);
+    hipLaunchKernelGGL(k_entropy_counts, dim3(g), dim3(kBlock), 0, s, hist, bins, cc, part);
+    hipLaunchKernelGGL(k_entropy_final, dim3(1), dim3(kBlock), 0, s, (const uint32_t *)cc,
+                       (const EntPartial *)part, g, result);
     return hipGetLastError();
 }
 
