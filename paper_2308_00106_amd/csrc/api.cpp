@@ -10,6 +10,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <limits>
+#include <set>
 
 #include "device_common.h"
 #include "runtime.h"
@@ -244,6 +245,17 @@ static mxe_status ensure_slab(mxe_ctx *ctx, Matrix &A, int kclass, int units, hi
     return MXE_OK;
 }
 
+static void drop_slab(mxe_ctx *ctx, Matrix &A, const Matrix::Slab &sl, hipStream_t s) {
+    const uint64_t bytes = 4ull * slab_offsets_count(sl.g) +
+                           (uint64_t)A.nnz * (4ull + (uint64_t)val_bytes_of(A.storage));
+    for (void *p : {(void *)sl.off, (void *)sl.idx, sl.val}) {
+        A.allocs.erase(std::remove(A.allocs.begin(), A.allocs.end(), p), A.allocs.end());
+        (void)hipFreeAsync(p, s);
+    }
+    A.bytes -= bytes;
+    ctx->used -= bytes;
+}
+
 // Arguments for one launch of `variant`, building what the variant needs.
 static mxe_status prepare_args(mxe_ctx *ctx, Matrix &A, int variant, int32_t k, const void *X,
                                int64_t ldx, void *Y, int64_t ldy, hipStream_t s, SpmvArgs *a) {
@@ -288,6 +300,8 @@ static mxe_status tune(mxe_ctx *ctx, Matrix &A, int32_t k, hipStream_t s, TuneRe
                           slab_bytes_of(units), &g))
             cands.push_back(MXE_VARIANT(MXE_VAR_SLAB, units));
     }
+    std::set<std::pair<int, int>> had;                // layouts other work may be using
+    for (const auto &kv : A.slabs) had.insert(kv.first);
     hipEvent_t e0, e1;
     MXE_HIP(hipEventCreate(&e0));
     MXE_HIP(hipEventCreate(&e1));
@@ -333,6 +347,17 @@ static mxe_status tune(mxe_ctx *ctx, Matrix &A, int32_t k, hipStream_t s, TuneRe
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
+    // column-slab layouts built here for this k class and not chosen are freed
+    // (stream-ordered after the timing launches)
+    for (auto it = A.slabs.begin(); it != A.slabs.end();) {
+        if (it->first.first == kc && !had.count(it->first) &&
+            (result != MXE_OK || MXE_VARIANT(MXE_VAR_SLAB, it->first.second) != r.variant)) {
+            drop_slab(ctx, A, it->second, s);
+            it = A.slabs.erase(it);
+        } else {
+            ++it;
+        }
+    }
     if (result != MXE_OK) return result;
     ctx->tuned[tune_key(A, k)] = r;
     if (out) *out = r;

@@ -150,4 +150,69 @@ __device__ inline float bf16_to_f32(uint16_t b) {
     return __uint_as_float((uint32_t)b << 16);
 }
 
+// Inclusive segmented scan over a wavefront whose keys never decrease
+// (equal keys are adjacent; real keys stay below 0xfffffffe, padding lanes
+// carry 0xffffffff after every real one), on DPP lane moves instead of LDS
+// permutes:
+// four row_shr steps inside each row of 16 lanes, then row_bcast:15 into rows
+// 1 and 3 and row_bcast:31 into rows 2 and 3. A lane adds the moved value only
+// when it carries its own key; moves from outside a row read key 0 and value
+// 0 (adding nothing), and rows a broadcast skips keep a key no row can have.
+template <int CTRL>
+__device__ inline uint32_t dpp_shr_u32(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, CTRL, 0xf, 0xf, true);
+}
+template <int CTRL, int RMASK>
+__device__ inline uint32_t dpp_bcast_u32(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_update_dpp((int)0xfffffffeu, (int)v, CTRL, RMASK, 0xf, false);
+}
+template <int CTRL>
+__device__ inline double dpp_shr(double v) {
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xf, 0xf, true);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xf, 0xf, true);
+    return __hiloint2double(hi, lo);
+}
+template <int CTRL>
+__device__ inline float dpp_shr(float v) {
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xf, 0xf, true));
+}
+template <int CTRL, int RMASK>
+__device__ inline double dpp_bcast(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, RMASK, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, RMASK, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+template <int CTRL, int RMASK>
+__device__ inline float dpp_bcast(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, RMASK, 0xf, false));
+}
+
+template <int CTRL, typename T, int KM>
+__device__ inline void scan_shr(uint32_t key, T (&v)[KM]) {
+    const bool take = dpp_shr_u32<CTRL>(key) == key;
+#pragma unroll
+    for (int q = 0; q < KM; ++q) {
+        const T m = dpp_shr<CTRL>(v[q]);
+        v[q] += take ? m : T(0);
+    }
+}
+template <int CTRL, int RMASK, typename T, int KM>
+__device__ inline void scan_bcast(uint32_t key, T (&v)[KM]) {
+    const bool take = dpp_bcast_u32<CTRL, RMASK>(key) == key;
+#pragma unroll
+    for (int q = 0; q < KM; ++q) {
+        const T m = dpp_bcast<CTRL, RMASK>(v[q]);
+        v[q] += take ? m : T(0);
+    }
+}
+template <typename T, int KM>
+__device__ inline void segmented_scan(uint32_t key, T (&v)[KM]) {
+    scan_shr<0x111>(key, v);            // row_shr:1
+    scan_shr<0x112>(key, v);            // row_shr:2
+    scan_shr<0x114>(key, v);            // row_shr:4
+    scan_shr<0x118>(key, v);            // row_shr:8
+    scan_bcast<0x142, 0xa>(key, v);     // row_bcast:15 -> rows 1, 3
+    scan_bcast<0x143, 0xc>(key, v);     // row_bcast:31 -> rows 2, 3
+}
+
 }  // namespace mxe

@@ -473,16 +473,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_coo(int32_t nrows, int64_t nnz,
 #pragma unroll
             for (int q = 0; q < KM; ++q) prod[q] += carry[q];
         }
-#pragma unroll
-        for (int d = 1; d < kWave; d <<= 1) {                 // inclusive segmented scan by row
-            const uint32_t kd = __shfl_up(key, d);
-            const bool take = lane >= d && kd == key;
-#pragma unroll
-            for (int q = 0; q < KM; ++q) {
-                const T v = __shfl_up(prod[q], d);
-                if (take) prod[q] += v;
-            }
-        }
+        segmented_scan<T, KM>(key, prod);                      // inclusive, by row
         const uint32_t nxt = __shfl_down(key, 1);
         const bool seg_end = valid && (lane == kWave - 1 || nxt != key);
         const bool to_next = seg_end && e + 1 < e1 && nr == (int32_t)key;

@@ -397,3 +397,26 @@ def test_coo_rows_across_many_tiles(ctx):
         ref = oracle.coo_spmm(A0.nrows, oracle.coo_rows(A0.row_ptr), A0.col, A0.val, X)
         assert np.array_equal(Y.cpu().numpy()[lens == 0], ref[lens == 0])    # exact zeros
     ctx.release(A)
+
+
+def test_tuning_keeps_only_the_chosen_slab_layout(ctx):
+    """The autotuner times several column-slab layouts; afterwards the matrix
+    holds at most the one it chose (HBM accounting)."""
+    A0 = synth.config2(1, n=600_000)
+    A = ctx.register(A0)
+    B = ctx.permute(A, 3)
+    before = ctx.matrix_info(B).device_bytes
+    v = ctx.tune(B, 1)
+    delta = ctx.matrix_info(B).device_bytes - before
+    layout = A0.nnz * 12                                  # uint32 word + FP64 value per entry
+    if (v & 0xf00) == mx.VAR_SLAB:
+        assert layout <= delta < layout + 4 * (1 << 22), (hex(v), delta)
+    else:
+        assert delta == 0, (hex(v), delta)
+    x = torch_vec(synth.vector(A0.ncols, 2), torch.float64)
+    y = torch.empty(A0.nrows, dtype=torch.float64, device="cuda")
+    ctx.spmv(B, x, y, flags=mx.SPACE_ORIGINAL)
+    torch.cuda.synchronize()
+    assert spmv_error(A0, synth.vector(A0.ncols, 2), y.cpu().numpy(), "f64") <= TOL["f64"]
+    ctx.release(B)
+    ctx.release(A)
