@@ -38,11 +38,21 @@ def spmv_bytes(nrows, ncols, nnz, val_bytes, vec_bytes, k=1):
     return nnz * (val_bytes + 4) + (nrows + 1) * 4 + k * (ncols + nrows) * vec_bytes
 
 
-def kernel_source_hash() -> str:
+def kernel_source_hash(variant_hex: str = "0x300") -> str:
+    """Hash of the sources the measured SpMV kernel is built from: its kernel
+    file (column-slab or row kernels), the shared device helpers and, for the
+    slab kernel, its layout descriptor."""
+    import re
+    csrc = os.path.join(ROOT, "paper_2308_00106_amd", "csrc")
+    slab = (int(variant_hex, 16) & 0xf00) == 0x300
     h = hashlib.sha256()
-    for f in ("kernels_spmv.hip", "kernels_slab.hip", "device_common.h", "internal.h"):
-        with open(os.path.join(ROOT, "paper_2308_00106_amd", "csrc", f), "rb") as fh:
+    for f in ("kernels_slab.hip" if slab else "kernels_spmv.hip", "device_common.h"):
+        with open(os.path.join(csrc, f), "rb") as fh:
             h.update(fh.read())
+    if slab:
+        with open(os.path.join(csrc, "internal.h")) as fh:
+            m = re.search(r"struct SlabGeom \{.*?\};", fh.read(), re.S)
+        h.update(m.group(0).encode() if m else b"")
     return h.hexdigest()[:16]
 
 
@@ -54,7 +64,7 @@ def measured_traffic(variant_hex: str):
             t = json.load(f)
     except (OSError, ValueError):
         return None
-    if t.get("kernel_source_hash") != kernel_source_hash() or t.get("variant") != variant_hex:
+    if t.get("variant") != variant_hex or t.get("kernel_source_hash") != kernel_source_hash(variant_hex):
         return None
     return t.get("bytes_per_launch")
 

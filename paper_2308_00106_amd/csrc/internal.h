@@ -18,7 +18,7 @@ size_t scan_ws_bytes(int64_t n);
 hipError_t launch_exclusive_scan(const int32_t *in, int32_t *out, int64_t n, void *ws,
                                  hipStream_t s);
 
-// ---- random permutation (keys + bucket sort) ------------------------------
+// ---- random permutation (keys + LDS radix / bucket sort) --------------------
 // perm: new-to-old, inv: old-to-new. Workspace: random_perm_ws_bytes(n).
 size_t random_perm_ws_bytes(int64_t n);
 hipError_t launch_random_perm(int64_t n, uint64_t stream_seed, int32_t *perm, int32_t *inv,

@@ -3,11 +3,14 @@
 //
 // The random permutation (Section 3; Eq. 1) is the stable ascending order of
 // 64-bit SplitMix64 keys. Because the keys are a pure function of the index,
-// they are never stored: a most-significant-digit bucket pass splits the
-// index range by the top b key bits (b chosen so a bucket holds ~30 items),
-// and one wavefront per bucket then ranks its items by (key, index) in
-// registers. Two light passes over 4-byte indices replace the eight
-// read-write passes of an LSD radix sort over 12-byte (key, index) pairs.
+// they are never stored. Up to 8.4M indices, an LDS radix pass buckets the
+// indices by the top 10-12 key bits (per-workgroup LDS histograms, a scan,
+// an LDS-cursor scatter of 4-byte indices) and one workgroup per bucket of
+// ~2K sorts it in LDS (split by the next 8 bits, then a rank by (key, index)
+// inside sub-buckets of ~8). Larger ranges take a global bucket path (device
+// atomics, buckets of ~30 ranked by one wavefront each). Either way two light
+// passes over 4-byte indices replace the eight read-write passes of an LSD
+// radix sort over 12-byte (key, index) pairs.
 #include "device_common.h"
 #include "internal.h"
 
@@ -125,7 +128,7 @@ __global__ __launch_bounds__(kBlock) void k_scan_tiles(const int32_t *in, int32_
     }
 }
 
-// ---- random permutation ------------------------------------------------------
+// ---- random permutation: global bucket path (above 8.4M indices) -------------
 
 inline int bucket_bits(int64_t n) {
     int b = 0;
