@@ -315,6 +315,19 @@ def main():
     value = reps * nbytes / dt / 1e9
     traffic = measured_traffic(f"0x{var_b:x}")
     ceiling = hbm_ceiling(stream)
+    # the product's x reads are nnz random 8-byte gathers: its gather rate against
+    # the device's measured ceiling, for an XCD-local slab (as the slab kernel
+    # reads x) and for the whole of x
+    slab_units = var_b & 0xff if (var_b & 0xf00) == 0x300 else 16
+    g_slab = ctx.probe_gather(8 * (slab_units << 16), A0.nnz, per_xcd=True, stream=stream)
+    g_all = ctx.probe_gather(A0.ncols * 8 // 64 * 64, A0.nnz, per_xcd=False, stream=stream)
+    gather = {"achieved_gps": round(A0.nnz / (perm_us * 1e-6) / 1e9, 1),
+              "ceiling_slab_per_xcd_gps": round(g_slab / 1e9, 1),
+              "ceiling_whole_x_gps": round(g_all / 1e9, 1),
+              "frac_of_slab_ceiling": round(A0.nnz / (perm_us * 1e-6) / g_slab, 4),
+              "what": f"random 8-byte gathers per second: the SpMV's {A0.nnz} x reads over its "
+                      f"time, and mxe_probe_gather's rate from a {slab_units * 64} KiB slab per "
+                      f"XCD and from all {A0.ncols * 8 >> 20} MiB of x"}
     out = {
         "metric": "SpMV GB/s (% HBM roofline), permuted vs original; served p50/p99 latency",
         "value": round(value, 2),
@@ -351,6 +364,7 @@ def main():
             "preprocessing": preprocessing,
         },
         "hbm_ceiling_measured": ceiling,
+        "gather_roofline": gather,
         "permuted_frac_of_measured_read_ceiling": round(perm_gbs / ceiling["read_gbs"], 4),
         "entropy_bits": {"original": h_a[0], "permuted": h_b[0], "max": 20.0},
         "max_normalized_error": err,

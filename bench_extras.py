@@ -155,6 +155,16 @@ def batch(ctx, log, count=64, replays=20):
     e1.record(stream)
     e1.synchronize()
     us = e0.elapsed_time(e1) * 1e3 / replays
+    # reference: the same products one launch per item, each with its own tuned variant
+    for h, X, Y in items:
+        ctx.spmv(h, X, Y, stream=stream)
+    e0.record(stream)
+    for _ in range(5):
+        for h, X, Y in items:
+            ctx.spmv(h, X, Y, stream=stream)
+    e1.record(stream)
+    e1.synchronize()
+    us_items = e0.elapsed_time(e1) * 1e3 / 5
     nb = sum(_bytes(A, 4, 4, k) for A, k in zip(mats, ks))
     flops = sum(2 * A.nnz * k for A, k in zip(mats, ks))
     # error of one member against the FP64 oracle (permuted space)
@@ -172,6 +182,7 @@ def batch(ctx, log, count=64, replays=20):
            "k_mix": {str(k): ks.count(k) for k in sorted(set(ks))}, "us_per_batch": round(us, 1),
            "gbs": round(nb / (us * 1e-6) / 1e9, 1), "gflops": round(flops / (us * 1e-6) / 1e9, 1),
            "bytes_per_batch": nb, "max_normalized_error_sample": err,
+           "us_one_launch_per_item_tuned": round(us_items, 1),
            "launch": "one persistent kernel per batch, replayed from a HIP graph"}
     log(f"batch: {out}")
     return out

@@ -219,6 +219,17 @@ mxe_status mxe_scatter_y(mxe_ctx *ctx, mxe_mat b, int32_t k, const void *Yp, int
 #define MXE_VAR_COO     0x500
 #define MXE_VARIANT(family, lanes) ((family) | (lanes))
 
+/* Measures the device's random 8-byte gather rate, the ceiling of a sparse
+ * product whose x reads are scattered (Section 3's max-entropy matrices): a
+ * kernel issues about `gathers` loads at LCG-drawn positions of a zeroed
+ * table of `table_bytes` (8 .. 2^34, a multiple of 64), each XCD confined to
+ * its own eighth of the table when per_xcd != 0 (as the column-slab product
+ * confines it to a slab). *gathers_per_s = loads issued / kernel time (HIP
+ * events on `stream`). Allocates the table from the stream-ordered pool;
+ * synchronizes. A diagnostic: no result of the method depends on it. */
+mxe_status mxe_probe_gather(mxe_ctx *ctx, int64_t table_bytes, int64_t gathers, int32_t per_xcd,
+                            void *stream, double *gathers_per_s);
+
 /* Times the candidate variants for (m, k) on the device and caches the
  * fastest; returns it in *variant (may be NULL). Synchronizes. */
 mxe_status mxe_tune(mxe_ctx *ctx, mxe_mat m, int32_t k, void *stream, int32_t *variant);

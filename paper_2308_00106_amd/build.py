@@ -16,7 +16,8 @@ CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libmxe.so")
 
-SOURCES = ["kernels_csr.hip", "kernels_entropy.hip", "kernels_spmv.hip", "kernels_slab.hip", "api.cpp", "serve.cpp"]
+SOURCES = ["kernels_csr.hip", "kernels_entropy.hip", "kernels_spmv.hip", "kernels_slab.hip",
+           "kernels_probe.hip", "api.cpp", "serve.cpp"]
 HEADERS = ["device_common.h", "internal.h", "runtime.h"]
 
 ARCH = "gfx950"

@@ -897,6 +897,37 @@ mxe_status mxe_tune(mxe_ctx *ctx, mxe_mat m, int32_t k, void *stream, int32_t *v
     return MXE_OK;
 }
 
+mxe_status mxe_probe_gather(mxe_ctx *ctx, int64_t table_bytes, int64_t gathers, int32_t per_xcd,
+                            void *stream, double *gathers_per_s) {
+    if (!ctx || !gathers_per_s) return fail(MXE_ERR_INVALID_ARG, "ctx or gathers_per_s is NULL");
+    if (table_bytes < 64 || table_bytes > (int64_t(1) << 34) || table_bytes % 64)
+        return fail(MXE_ERR_INVALID_ARG, "table_bytes must be a multiple of 64 in [64, 2^34]");
+    if (gathers < 1 || gathers > (int64_t(1) << 36)) return fail(MXE_ERR_INVALID_ARG, "gathers out of range");
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    DeviceGuard g(ctx->device);
+    hipStream_t s = (hipStream_t)stream;
+    const int32_t grid = ctx->cu_count * 8;
+    Scratch ws;
+    mxe_status st;
+    if ((st = ws.alloc(probe_gather_ws_bytes(table_bytes, grid), s))) return st;
+    MXE_HIP(hipMemsetAsync(ws.p, 0, (size_t)table_bytes, s));
+    hipEvent_t e0, e1;
+    MXE_HIP(hipEventCreate(&e0));
+    MXE_HIP(hipEventCreate(&e1));
+    hipError_t e = launch_probe_gather(table_bytes, gathers, per_xcd, ws.p, grid, s);   // warm-up
+    if (e == hipSuccess) e = hipEventRecord(e0, s);
+    if (e == hipSuccess) e = launch_probe_gather(table_bytes, gathers, per_xcd, ws.p, grid, s);
+    if (e == hipSuccess) e = hipEventRecord(e1, s);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (e != hipSuccess) return hip_fail(e, "gather probe");
+    *gathers_per_s = (double)probe_gathers_issued(gathers, grid) / (ms * 1e-3);
+    return MXE_OK;
+}
+
 mxe_status mxe_set_variant(mxe_ctx *ctx, mxe_mat m, int32_t k, int32_t variant) {
     if (!ctx) return fail(MXE_ERR_INVALID_ARG, "ctx is NULL");
     if (k < 1) return fail(MXE_ERR_INVALID_ARG, "k must be >= 1");

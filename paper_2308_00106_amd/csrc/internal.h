@@ -179,6 +179,14 @@ hipError_t launch_spmv_batch(const BatchDesc *descs, const int32_t *qent, const 
                              int32_t *counters, int32_t grid, int vtype, hipStream_t s);
 int32_t batch_grid_size();
 
+// ---- random-gather rate probe -------------------------------------------------
+// ws: probe_gather_ws_bytes; the table is ws's first table_bytes (8-byte
+// values, any contents). Issues probe_gathers_issued(gathers, grid) gathers.
+size_t probe_gather_ws_bytes(int64_t table_bytes, int32_t grid);
+hipError_t launch_probe_gather(int64_t table_bytes, int64_t gathers, int per_xcd, void *ws,
+                               int32_t grid, hipStream_t s);
+int64_t probe_gathers_issued(int64_t gathers, int32_t grid);
+
 // ---- serving: pack / unpack merged right-hand sides -------------------------
 // Copies k columns between a caller matrix (ld) and columns [c0, c0+k) of a
 // packed matrix (ldp); elem_bytes 8 or 4.

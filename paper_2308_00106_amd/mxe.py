@@ -91,6 +91,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "mxe_scatter_y": ([P, i64, i32, P, i64, P, i64, P], st),
         "mxe_tune": ([P, i64, i32, P, P], st),
         "mxe_set_variant": ([P, i64, i32, i32], st),
+        "mxe_probe_gather": ([P, i64, i64, i32, P, P], st),
         "mxe_spmv_batch": ([P, i32, P, P], st),
         "mxe_batch_create": ([P, i32, P, P], st),
         "mxe_batch_launch": ([P, i64, P, P], st),
@@ -339,6 +340,15 @@ class Context:
         v = ctypes.c_int32()
         _check(self._lib.mxe_tune(self._h, m, k, _stream_ptr(stream), ctypes.byref(v)), "mxe_tune")
         return v.value
+
+    def probe_gather(self, table_bytes: int, gathers: int, per_xcd: bool = False,
+                     stream=None) -> float:
+        """Random 8-byte gathers per second from a table of table_bytes."""
+        rate = ctypes.c_double()
+        _check(self._lib.mxe_probe_gather(self._h, table_bytes, gathers, int(per_xcd),
+                                          _stream_ptr(stream), ctypes.byref(rate)),
+               "mxe_probe_gather")
+        return rate.value
 
     def set_variant(self, m: int, k: int, var: int) -> None:
         _check(self._lib.mxe_set_variant(self._h, m, k, var), "mxe_set_variant")

@@ -420,3 +420,13 @@ def test_tuning_keeps_only_the_chosen_slab_layout(ctx):
     assert spmv_error(A0, synth.vector(A0.ncols, 2), y.cpu().numpy(), "f64") <= TOL["f64"]
     ctx.release(B)
     ctx.release(A)
+
+
+def test_gather_probe(ctx):
+    r_slab = ctx.probe_gather(8 * (12 << 16), 2_000_000, per_xcd=True)
+    r_all = ctx.probe_gather(16 << 20, 2_000_000)
+    assert 1e9 < r_slab < 1e13 and 1e9 < r_all < 1e13
+    for bad in ((0, 10), (100, 10), (1 << 35, 10), (1024, 0)):
+        with pytest.raises(mx.MxeError) as e:
+            ctx.probe_gather(*bad)
+        assert e.value.status == mx.ERR_INVALID_ARG
