@@ -16,6 +16,7 @@ Parity status per function (what pins it is in tests/test_oracle.py):
   entropy                           pinned (closed forms, uniform fill, scipy)
   spmm / spmv                       pinned (dense brute force, scipy)
   coo_rows, coo_spmm                pinned (dense brute force, scipy COO, shuffled entry order)
+  spmm_semiring                     pinned (dense brute force, scipy shortest paths, BFS reachability)
   entropy_levels                    pinned (uniform fill per level, hand cases, L = 1 is the global H)
   gradient_permutation, permute_gradient
                                     pinned (hand-built step profile, ties, edges, scipy slicing)
@@ -69,6 +70,8 @@ def _c():
         lib.orc_spmm.argtypes = [i32, P, P, P, i32, P, i64, P, i64]
         lib.orc_spmm_parallel.argtypes = [i32, P, P, P, i32, P, i64, P, i64]
         lib.orc_coo_spmm.argtypes = [i32, i64, P, P, P, i32, P, i64, P, i64]
+        lib.orc_spmm_min_plus.argtypes = [i32, P, P, P, i32, P, i64, P, i64]
+        lib.orc_spmm_or_and.argtypes = [i32, P, P, P, i32, P, i64, P, i64]
         lib.orc_omp_max_threads.restype = ctypes.c_int
         lib.orc_round_f32.argtypes = [i64, P, P]
         lib.orc_round_bf16.argtypes = [i64, P, P]
@@ -263,6 +266,23 @@ def spmm(nrows: int, row_ptr, col, val, X: np.ndarray) -> np.ndarray:
 
 def spmv(A, x):
     return spmm(A.nrows, A.row_ptr, A.col, A.val, x)
+
+
+MIN_PLUS, OR_AND = 1, 2
+
+
+def spmm_semiring(semiring: int, nrows: int, row_ptr, col, val, X: np.ndarray) -> np.ndarray:
+    """Y = A X over (min, +) (semiring 1: y_i = min of val + x over row i's
+    stored entries, +inf for an empty row) or (or, and) (semiring 2: y_i = 1
+    if a stored nonzero meets a nonzero x, else 0), Section 2."""
+    X = np.asarray(X, dtype=np.float64)
+    k = 1 if X.ndim == 1 else X.shape[1]
+    X2 = np.ascontiguousarray(X.reshape(len(X), k))
+    Y = np.empty((nrows, k), dtype=np.float64)
+    rp, c, v = _c_i32(row_ptr), _c_i32(col), _c_f64(val)
+    fn = {MIN_PLUS: _c().orc_spmm_min_plus, OR_AND: _c().orc_spmm_or_and}[semiring]
+    fn(nrows, _p(rp), _p(c), _p(v), k, _p(X2), k, _p(Y), k)
+    return Y[:, 0].copy() if X.ndim == 1 else Y
 
 
 def coo_rows(row_ptr) -> np.ndarray:

@@ -12,6 +12,7 @@
  *
  * Build: gcc -O2 -fopenmp -shared -fPIC mxe_oracle.c -o liboracle.so
  */
+#include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -177,6 +178,39 @@ void orc_spmm(int32_t nrows, const int32_t *rp, const int32_t *col, const double
     }
 }
 
+/* SpMV / SpMM over other semirings (Section 2 notes the product extends to */
+/* them): (min, +), y_i = min over row i's stored entries of V[l] + x[COL[l]] */
+/* (+inf for an empty row, the shortest-path step), and Boolean (or, and),   */
+/* y_i = 1 if some stored V[l] != 0 meets x[COL[l]] != 0, else 0             */
+/* (reachability). min and or are exact, so the order does not matter.      */
+void orc_spmm_min_plus(int32_t nrows, const int32_t *rp, const int32_t *col, const double *val,
+                       int32_t k, const double *x, int64_t ldx, double *y, int64_t ldy)
+{
+    for (int32_t i = 0; i < nrows; ++i) {
+        for (int32_t c = 0; c < k; ++c) {
+            double acc = INFINITY;
+            for (int32_t e = rp[i]; e < rp[i + 1]; ++e) {
+                double t = val[e] + x[(int64_t)col[e] * ldx + c];
+                if (t < acc) acc = t;
+            }
+            y[(int64_t)i * ldy + c] = acc;
+        }
+    }
+}
+
+void orc_spmm_or_and(int32_t nrows, const int32_t *rp, const int32_t *col, const double *val,
+                     int32_t k, const double *x, int64_t ldx, double *y, int64_t ldy)
+{
+    for (int32_t i = 0; i < nrows; ++i) {
+        for (int32_t c = 0; c < k; ++c) {
+            int any = 0;
+            for (int32_t e = rp[i]; e < rp[i + 1]; ++e)
+                if (val[e] != 0.0 && x[(int64_t)col[e] * ldx + c] != 0.0) any = 1;
+            y[(int64_t)i * ldy + c] = any ? 1.0 : 0.0;
+        }
+    }
+}
+
 /* COO SpMV / SpMM (Section 2's coordinate format): Y starts at zero and   */
 /* every stored entry l, in storage order, adds V[l] * x[COL[l]] to row     */
 /* ROW[l]. On entries sorted by row this adds each row's terms in the same  */
@@ -228,7 +262,6 @@ int orc_omp_max_threads(void)
 /* FP32, which would round twice.                                           */
 /* ------------------------------------------------------------------------ */
 
-#include <math.h>
 
 void orc_round_f32(int64_t n, const double *in, float *out)
 {

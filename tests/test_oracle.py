@@ -311,6 +311,61 @@ def test_coo_spmv_dense_brute_force_and_scipy():
     assert np.all(Y[np.diff(A.row_ptr) == 0] == 0.0)   # empty rows are exactly zero
 
 
+def test_semiring_products_dense_brute_force():
+    A = synth.random_csr(30, 25, 0.2, 14, empty_rows=0.2)
+    X = synth.vector(25, 15, k=2)
+    X[3] = 0.0                                       # zeros in x matter for (or, and)
+    Amp = oracle.spmm_semiring(oracle.MIN_PLUS, A.nrows, A.row_ptr, A.col, A.val, X)
+    Aor = oracle.spmm_semiring(oracle.OR_AND, A.nrows, A.row_ptr, A.col, A.val, X)
+    for i in range(A.nrows):
+        cols = A.col[A.row_ptr[i]:A.row_ptr[i + 1]]
+        vals = A.val[A.row_ptr[i]:A.row_ptr[i + 1]]
+        for c in range(2):
+            terms = [v + X[j, c] for j, v in zip(cols, vals)]
+            assert Amp[i, c] == (min(terms) if terms else np.inf)
+            assert Aor[i, c] == float(any(v != 0 and X[j, c] != 0 for j, v in zip(cols, vals)))
+
+
+def test_min_plus_iteration_gives_shortest_paths():
+    """Bellman-Ford as repeated (min, +) products with the transposed weight
+    matrix equals scipy's shortest paths; integer weights keep sums exact."""
+    import scipy.sparse as sp
+    from scipy.sparse.csgraph import shortest_path
+    rng = np.random.default_rng(4)
+    n = 60
+    W = synth.random_csr(n, n, 0.06, 16)
+    W.val = rng.integers(1, 10, size=W.nnz).astype(np.float64)
+    Wt = sp.csr_matrix((W.val, W.col, W.row_ptr), shape=(n, n)).T.tocsr()
+    Wt.sort_indices()
+    for s0 in (0, 7):
+        d = np.full(n, np.inf)
+        d[s0] = 0.0
+        for _ in range(n - 1):
+            d = np.minimum(d, oracle.spmm_semiring(oracle.MIN_PLUS, n, Wt.indptr, Wt.indices,
+                                                   Wt.data, d))
+        ref = shortest_path(sp.csr_matrix((W.val, W.col, W.row_ptr), shape=(n, n)),
+                            directed=True, indices=s0)
+        assert np.array_equal(d, ref)
+
+
+def test_or_and_iteration_gives_reachability():
+    import scipy.sparse as sp
+    from scipy.sparse.csgraph import breadth_first_order
+    n = 80
+    W = synth.random_csr(n, n, 0.025, 17)
+    Wt = sp.csr_matrix((W.val, W.col, W.row_ptr), shape=(n, n)).T.tocsr()
+    Wt.sort_indices()
+    for s0 in (0, 11):
+        r = np.zeros(n)
+        r[s0] = 1.0
+        for _ in range(n):
+            r = np.maximum(r, oracle.spmm_semiring(oracle.OR_AND, n, Wt.indptr, Wt.indices,
+                                                   Wt.data, r))
+        order = breadth_first_order(sp.csr_matrix((W.val, W.col, W.row_ptr), shape=(n, n)), s0,
+                                    directed=True, return_predecessors=False)
+        assert set(np.nonzero(r)[0].tolist()) == set(order.tolist())
+
+
 def test_spmm_parallel_equals_serial():
     A = synth.random_csr(500, 300, 0.05, 12)
     X = np.ascontiguousarray(synth.vector(300, 13, k=3))
