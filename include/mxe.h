@@ -189,6 +189,19 @@ mxe_status mxe_entropy_levels(mxe_ctx *ctx, mxe_mat m, int32_t grid_rows, int32_
 mxe_status mxe_spmv(mxe_ctx *ctx, mxe_mat m, int32_t k, const void *X, int64_t ldx,
                     void *Y, int64_t ldy, uint32_t flags, void *stream);
 
+/* Semirings for mxe_spmv_semiring (Section 2 defines the product on (+, *)
+ * and notes it extends to others). */
+#define MXE_SR_PLUS_TIMES 0   /* y_i = sum of v * x: the same as mxe_spmv */
+#define MXE_SR_MIN_PLUS   1   /* y_i = min over row i's stored entries of v + x; +inf if none */
+#define MXE_SR_OR_AND     2   /* y_i = 1 if a stored v != 0 meets x != 0 in row i, else 0 */
+
+/* Y = M X over `semiring`, otherwise as mxe_spmv (k >= 1, index spaces,
+ * storage and accumulation types). (min, +) and (or, and) results do not
+ * depend on the order of the terms, so they are exact: the same bits as a
+ * sequential loop over each row in the accumulation type. */
+mxe_status mxe_spmv_semiring(mxe_ctx *ctx, mxe_mat m, int32_t semiring, int32_t k, const void *X,
+                             int64_t ldx, void *Y, int64_t ldy, uint32_t flags, void *stream);
+
 /* x' = P_c^-1 x: Xp[j'] = X[cperm[j']] (k columns). */
 mxe_status mxe_gather_x(mxe_ctx *ctx, mxe_mat b, int32_t k, const void *X, int64_t ldx,
                         void *Xp, int64_t ldxp, void *stream);

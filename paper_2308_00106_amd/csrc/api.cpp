@@ -845,6 +845,46 @@ mxe_status mxe_spmv(mxe_ctx *ctx, mxe_mat m, int32_t k, const void *X, int64_t l
     return spmv_internal(ctx, *A, k, X, ldx, Y, ldy, flags, (hipStream_t)stream);
 }
 
+// Y = M X over (min, +) or (or, and), 16 columns per launch; for a permuted
+// matrix in the original index space X is gathered by cperm and Y scattered
+// by rperm around the product, as for (+, *).
+static mxe_status semiring_core(Matrix &A, int semiring, int32_t k, const void *X, int64_t ldx,
+                                void *Y, int64_t ldy, hipStream_t s) {
+    const int eb = elem_bytes_of(A.storage);
+    for (int32_t c0 = 0; c0 < k; c0 += 16) {
+        SpmvArgs a = make_args(A, std::min<int32_t>(16, k - c0), (const char *)X + (size_t)c0 * eb,
+                               ldx, (char *)Y + (size_t)c0 * eb, ldy);
+        MXE_HIP(launch_spmv_semiring(a, semiring, s));
+    }
+    return MXE_OK;
+}
+
+mxe_status mxe_spmv_semiring(mxe_ctx *ctx, mxe_mat m, int32_t semiring, int32_t k, const void *X,
+                             int64_t ldx, void *Y, int64_t ldy, uint32_t flags, void *stream) {
+    if (semiring == MXE_SR_PLUS_TIMES) return mxe_spmv(ctx, m, k, X, ldx, Y, ldy, flags, stream);
+    if (!ctx) return fail(MXE_ERR_INVALID_ARG, "ctx is NULL");
+    if (semiring != MXE_SR_MIN_PLUS && semiring != MXE_SR_OR_AND)
+        return fail(MXE_ERR_INVALID_ARG, "unknown semiring");
+    if (flags & ~MXE_SPACE_ORIGINAL) return fail(MXE_ERR_INVALID_ARG, "unknown flags");
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    DeviceGuard g(ctx->device);
+    auto A = find_matrix(ctx, m);
+    if (!A) return fail(MXE_ERR_NOT_FOUND, "unknown matrix handle");
+    mxe_status st = check_dense(*A, k, X, ldx, Y, ldy);
+    if (st) return st;
+    hipStream_t s = (hipStream_t)stream;
+    if (!(flags & MXE_SPACE_ORIGINAL) || !A->rperm)
+        return semiring_core(*A, semiring, k, X, ldx, Y, ldy, s);
+    const int eb = elem_bytes_of(A->storage);
+    Scratch xp, yp;
+    if ((st = xp.alloc((size_t)eb * std::max(A->ncols, 1) * k, s))) return st;
+    if ((st = yp.alloc((size_t)eb * std::max(A->nrows, 1) * k, s))) return st;
+    MXE_HIP(launch_gather_rows(A->ncols, k, A->cperm, X, ldx, xp.p, k, eb, s));
+    if ((st = semiring_core(*A, semiring, k, xp.p, k, yp.p, k, s))) return st;
+    MXE_HIP(launch_scatter_rows(A->nrows, k, A->rperm, yp.p, k, Y, ldy, eb, s));
+    return MXE_OK;
+}
+
 mxe_status mxe_gather_x(mxe_ctx *ctx, mxe_mat b, int32_t k, const void *X, int64_t ldx, void *Xp,
                         int64_t ldxp, void *stream) {
     if (!ctx) return fail(MXE_ERR_INVALID_ARG, "ctx is NULL");

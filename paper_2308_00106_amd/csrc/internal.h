@@ -145,6 +145,8 @@ struct SpmvArgs {
 };
 
 size_t merge_ws_bytes(int32_t nrows, int64_t nnz);
+// Y = M X over MXE_SR_MIN_PLUS or MXE_SR_OR_AND (mxe.h), k <= 16.
+hipError_t launch_spmv_semiring(const SpmvArgs &a, int semiring, hipStream_t s);
 size_t coo_ws_bytes(int64_t nnz);                 // enough for k <= 16
 hipError_t launch_coo_rows(int32_t nrows, const int32_t *rp, int32_t *row, hipStream_t s);
 // variant: MXE_VARIANT(family, lanes) as in mxe.h

@@ -543,6 +543,85 @@ hipError_t coo_launch(const SpmvArgs &a, hipStream_t s) {
     return hipGetLastError();
 }
 
+// ---- other semirings (Section 2) --------------------------------------------------
+// L lanes per row take its entries in a lane stride and combine them with the
+// semiring's product, then an xor butterfly over the L lanes with its sum.
+// min and or are exact, so the order of the terms does not matter.
+
+template <int SR, typename T> struct Semiring;
+template <typename T> struct Semiring<MXE_SR_MIN_PLUS, T> {
+    __device__ static T zero() { return T(__builtin_inf()); }
+    __device__ static T mul(T a, T x) { return a + x; }
+    __device__ static T add(T p, T q) { return q < p ? q : p; }   // never NaN: see the header
+};
+template <typename T> struct Semiring<MXE_SR_OR_AND, T> {
+    __device__ static T zero() { return T(0); }
+    __device__ static T mul(T a, T x) { return (a != T(0) && x != T(0)) ? T(1) : T(0); }
+    __device__ static T add(T p, T q) { return (p != T(0) || q != T(0)) ? T(1) : T(0); }
+};
+
+template <typename V, typename T, int SR, int L, int KM>
+__global__ __launch_bounds__(kBlock) void k_spmv_semiring(int32_t nrows, const int32_t *__restrict__ rp,
+                                                          const int32_t *__restrict__ col,
+                                                          const V *__restrict__ val, int32_t k,
+                                                          const T *__restrict__ X, int64_t ldx,
+                                                          T *__restrict__ Y, int64_t ldy) {
+    using S = Semiring<SR, T>;
+    const int64_t gt = blockIdx.x * (int64_t)kBlock + threadIdx.x;
+    const int64_t row = gt / L;
+    const int lane = (int)(gt % L);
+    T acc[KM];
+#pragma unroll
+    for (int q = 0; q < KM; ++q) acc[q] = S::zero();
+    if (row < nrows) {                       // other lanes still join the butterfly
+        for (int32_t p = rp[row] + lane; p < rp[row + 1]; p += L) {
+            const T a = ValLoad<V, T>::get(val + p);
+            const T *xr = X + (int64_t)ld_stream(col + p) * ldx;
+#pragma unroll
+            for (int q = 0; q < KM; ++q)
+                if (KM == 1 || q < k) acc[q] = S::add(acc[q], S::mul(a, xr[q]));
+        }
+    }
+#pragma unroll
+    for (int off = L / 2; off > 0; off >>= 1)
+#pragma unroll
+        for (int q = 0; q < KM; ++q) acc[q] = S::add(acc[q], __shfl_xor(acc[q], off));
+    if (row < nrows && lane == 0)
+#pragma unroll
+        for (int q = 0; q < KM; ++q)
+            if (KM == 1 || q < k) Y[row * ldy + q] = acc[q];
+}
+
+template <typename V, typename T, int SR, int L>
+hipError_t semiring_by_k(const SpmvArgs &a, hipStream_t s) {
+    const int64_t grid = cdiv((int64_t)a.nrows * L, kBlock);
+#define MXE_SR_LAUNCH(KMV)                                                                         \
+    hipLaunchKernelGGL((k_spmv_semiring<V, T, SR, L, KMV>), dim3((unsigned)grid), dim3(kBlock), 0, \
+                       s, a.nrows, a.rp, a.col, (const V *)a.val, a.k, (const T *)a.X, a.ldx,      \
+                       (T *)a.Y, a.ldy)
+    if (a.k <= 1) MXE_SR_LAUNCH(1);
+    else if (a.k <= 4) MXE_SR_LAUNCH(4);
+    else MXE_SR_LAUNCH(16);
+#undef MXE_SR_LAUNCH
+    return hipGetLastError();
+}
+
+template <typename V, typename T, int SR>
+hipError_t semiring_by_lanes(const SpmvArgs &a, hipStream_t s) {
+    const bool long_rows = a.nrows > 0 && a.nnz / a.nrows > 16;
+    return long_rows ? semiring_by_k<V, T, SR, 32>(a, s) : semiring_by_k<V, T, SR, 8>(a, s);
+}
+
+template <int SR>
+hipError_t semiring_by_type(const SpmvArgs &a, hipStream_t s) {
+    switch (a.vtype) {
+    case VAL_F64: return semiring_by_lanes<double, double, SR>(a, s);
+    case VAL_F32: return semiring_by_lanes<float, float, SR>(a, s);
+    case VAL_BF16: return semiring_by_lanes<uint16_t, float, SR>(a, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
 // Persistent grid with one work queue per XCD (workgroups are dealt to the
 // 8 XCDs round-robin): a workgroup takes tiles from its own XCD's queue, whose
 // matrices' x then stays in that XCD's L2, and when it is empty from the
@@ -680,6 +759,16 @@ hipError_t spmv_t(const SpmvArgs &a, int variant, hipStream_t s) {
 size_t merge_ws_bytes(int32_t nrows, int64_t nnz) {
     const int64_t ntiles = std::max<int64_t>(1, cdiv((int64_t)nrows + nnz, kMergeTile));
     return ((sizeof(Coord) * (ntiles + 1) + 255) & ~255ull) + sizeof(Carry) * ntiles + 256;
+}
+
+hipError_t launch_spmv_semiring(const SpmvArgs &a, int semiring, hipStream_t s) {
+    if (a.nrows <= 0) return hipSuccess;
+    if (a.k < 1 || a.k > 16) return hipErrorInvalidValue;
+    switch (semiring) {
+    case MXE_SR_MIN_PLUS: return semiring_by_type<MXE_SR_MIN_PLUS>(a, s);
+    case MXE_SR_OR_AND: return semiring_by_type<MXE_SR_OR_AND>(a, s);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 size_t coo_ws_bytes(int64_t nnz) {

@@ -27,6 +27,7 @@ INPUT_DEVICE = OUTPUT_DEVICE = 0x1
 ROWS, COLS, GRADIENT = 0x1, 0x2, 0x4
 SPACE_PERMUTED, SPACE_ORIGINAL = 0x0, 0x1
 VAR_GROUP, VAR_BINNED, VAR_MERGE, VAR_SLAB, VAR_FIXED, VAR_COO = 0x000, 0x100, 0x200, 0x300, 0x400, 0x500
+SR_PLUS_TIMES, SR_MIN_PLUS, SR_OR_AND = 0, 1, 2
 
 
 def variant(family: int, lanes: int = 0) -> int:
@@ -92,6 +93,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "mxe_tune": ([P, i64, i32, P, P], st),
         "mxe_set_variant": ([P, i64, i32, i32], st),
         "mxe_probe_gather": ([P, i64, i64, i32, P, P], st),
+        "mxe_spmv_semiring": ([P, i64, i32, i32, P, i64, P, i64, u32, P], st),
         "mxe_spmv_batch": ([P, i32, P, P], st),
         "mxe_batch_create": ([P, i32, P, P], st),
         "mxe_batch_launch": ([P, i64, P, P], st),
@@ -317,6 +319,17 @@ class Context:
             raise ValueError("X and Y must have the same number of columns")
         _check(self._lib.mxe_spmv(self._h, m, kx, xp, ldx, yp, ldy, flags, _stream_ptr(stream)),
                "mxe_spmv")
+
+    def spmv_semiring(self, m: int, semiring: int, X, Y, flags: int = SPACE_PERMUTED,
+                      stream=None) -> None:
+        """Y = M X over SR_MIN_PLUS or SR_OR_AND (SR_PLUS_TIMES is spmv)."""
+        nrows, ncols, _ = self._meta[m]
+        xp, kx, ldx = _dense(X, ncols, self._fp64(m), "X")
+        yp, ky, ldy = _dense(Y, nrows, self._fp64(m), "Y")
+        if kx != ky:
+            raise ValueError("X and Y must have the same number of columns")
+        _check(self._lib.mxe_spmv_semiring(self._h, m, semiring, kx, xp, ldx, yp, ldy, flags,
+                                           _stream_ptr(stream)), "mxe_spmv_semiring")
 
     def gather_x(self, b: int, X, Xp, stream=None) -> None:
         _, ncols, _ = self._meta[b]

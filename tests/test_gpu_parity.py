@@ -430,3 +430,67 @@ def test_gather_probe(ctx):
         with pytest.raises(mx.MxeError) as e:
             ctx.probe_gather(*bad)
         assert e.value.status == mx.ERR_INVALID_ARG
+
+
+# --- other semirings: (min, +) and (or, and) ---------------------------------------
+
+def _semiring_x(ncols, k, seed):
+    X = synth.vector(ncols, seed, k=k)
+    X[np.random.default_rng(seed).random(X.shape) < 0.3] = 0.0     # zeros matter for (or, and)
+    return X
+
+
+@pytest.mark.parametrize("name,make", CSR_CASES)
+@pytest.mark.parametrize("k", [1, 3, 17])
+def test_semiring_products_bit_exact(ctx, name, make, k):
+    """FP64 storage: (min, +) and (or, and) equal the oracle bit for bit, in
+    the permuted space and, through the permutations, in A's space."""
+    A0 = make()
+    X = _semiring_x(A0.ncols, k, 7)
+    A = ctx.register(A0)
+    B = ctx.permute(A, 3)
+    rperm, cperm = ctx.get_permutation(B)
+    Bo = synth.CSR(A0.nrows, A0.ncols, *oracle.permute_csr(A0, rperm, cperm))
+    shape = (A0.nrows, k) if k > 1 else (A0.nrows,)
+    for sr in (mx.SR_MIN_PLUS, mx.SR_OR_AND):
+        for H, Ho, flags, Xin in ((A, A0, 0, X), (B, Bo, 0, X[cperm]),
+                                  (B, A0, mx.SPACE_ORIGINAL, X)):
+            Y = torch.full(shape, float("nan"), dtype=torch.float64, device="cuda")
+            ctx.spmv_semiring(H, sr, torch_vec(Xin, torch.float64), Y, flags=flags)
+            torch.cuda.synchronize()
+            ref = oracle.spmm_semiring(sr, Ho.nrows, Ho.row_ptr, Ho.col, Ho.val, Xin)
+            assert np.array_equal(Y.cpu().numpy(), ref.reshape(shape)), (name, sr, flags)
+    ctx.release(B)
+    ctx.release(A)
+
+
+@pytest.mark.parametrize("storage", ["f32", "bf16"])
+def test_semiring_products_reduced_storage(ctx, storage):
+    A0 = synth.config3(1, n=50_000)
+    X = _semiring_x(A0.ncols, 4, 8)
+    X32 = X.astype(np.float32).astype(np.float64)
+    A = ctx.register(A0, storage)
+    vals = oracle.stored_values(A0.val, storage)
+    for sr in (mx.SR_MIN_PLUS, mx.SR_OR_AND):
+        Y = torch.full((A0.nrows, 4), float("nan"), dtype=torch.float32, device="cuda")
+        ctx.spmv_semiring(A, sr, torch_vec(X, torch.float32), Y)
+        torch.cuda.synchronize()
+        got = Y.cpu().numpy().astype(np.float64)
+        ref = oracle.spmm_semiring(sr, A0.nrows, A0.row_ptr, A0.col, vals, X32)
+        if sr == mx.SR_OR_AND:
+            assert np.array_equal(got, ref)
+        else:                          # one FP32 rounding of each v + x, exact min
+            assert np.array_equal(np.isinf(got), np.isinf(ref))
+            fin = np.isfinite(ref)
+            assert np.all(np.abs(got[fin] - ref[fin]) <= 2.0 ** -23 * (np.abs(ref[fin]) + 2.0))
+    ctx.release(A)
+
+
+def test_semiring_rejects_unknown(ctx):
+    A = ctx.register(synth.config1(1))
+    x = torch.zeros(4096, dtype=torch.float64, device="cuda")
+    y = torch.zeros(4096, dtype=torch.float64, device="cuda")
+    with pytest.raises(mx.MxeError) as e:
+        ctx.spmv_semiring(A, 7, x, y)
+    assert e.value.status == mx.ERR_INVALID_ARG
+    ctx.release(A)
