@@ -13,6 +13,8 @@
               the tuned count-aware variant on the original, R, RC and
               gradient (G-R, G-RC) orderings, plus the hierarchical 2D
               entropy of each.
+  semiring    the n = 2,000,000 block-clustered matrix (FP64): (min, +) and
+              (or, and) products, original vs permuted, against the (+, *) one.
   serving     32 resident permuted matrices of 50k-2M rows (FP32), requests of
               1-8 right-hand sides on a random matrix; closed-loop saturation
               rate, then open-loop Poisson arrivals at 0.5 and 0.8 of it:
@@ -126,6 +128,38 @@ def heavy(ctx, log, n=2_000_000, reps=50):
         log(f"heavy {name}: {r}")
         if mode is not None:
             ctx.release(H)
+    ctx.release(A)
+    return out
+
+
+def semiring(ctx, log, n=2_000_000, reps=50):
+    import torch
+    from paper_2308_00106_amd import mxe as mx
+    stream = torch.cuda.current_stream()
+    A0 = synth.config2(1, n=n)
+    A = ctx.register(A0)
+    B = ctx.permute(A, 3, stream=stream)
+    nb = _bytes(A0, 8, 8, 1)
+    out = {"n": n, "nnz": A0.nnz}
+    for name, H in (("original", A), ("permuted", B)):
+        x = torch.from_numpy(synth.vector(A0.ncols, 2)).to(device="cuda")
+        y = torch.empty(A0.nrows, dtype=torch.float64, device="cuda")
+        r = {}
+        for sr_name, sr in (("min_plus", mx.SR_MIN_PLUS), ("or_and", mx.SR_OR_AND)):
+            ctx.spmv_semiring(H, sr, x, y, stream=stream)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(reps):
+                ctx.spmv_semiring(H, sr, x, y, stream=stream)
+            e1.record(stream)
+            e1.synchronize()
+            us = e0.elapsed_time(e1) * 1e3 / reps
+            r[sr_name] = {"us": round(us, 2), "gbs": round(nb / (us * 1e-6) / 1e9, 1)}
+        ctx.tune(H, 1, stream=stream)
+        r["plus_times_tuned_us"] = round(_time(ctx, H, x, y, reps, stream), 2)
+        out[name] = r
+        log(f"semiring {name}: {r}")
+    ctx.release(B)
     ctx.release(A)
     return out
 
@@ -282,5 +316,5 @@ def serving(ctx_unused, log, pool=32, warm=1000, n_req=20000):
 
 
 def run_all(ctx, log):
-    return {"skewed": skewed(ctx, log), "heavy": heavy(ctx, log), "batch": batch(ctx, log),
-            "serving": serving(ctx, log)}
+    return {"skewed": skewed(ctx, log), "heavy": heavy(ctx, log), "semiring": semiring(ctx, log),
+            "batch": batch(ctx, log), "serving": serving(ctx, log)}

@@ -196,9 +196,11 @@ mxe_status mxe_spmv(mxe_ctx *ctx, mxe_mat m, int32_t k, const void *X, int64_t l
 #define MXE_SR_OR_AND     2   /* y_i = 1 if a stored v != 0 meets x != 0 in row i, else 0 */
 
 /* Y = M X over `semiring`, otherwise as mxe_spmv (k >= 1, index spaces,
- * storage and accumulation types). (min, +) and (or, and) results do not
- * depend on the order of the terms, so they are exact: the same bits as a
- * sequential loop over each row in the accumulation type. */
+ * storage and accumulation types); the kernel is the column-slab one when the
+ * matrix's autotuned (+, *) variant for k is (tuning first if needed), else
+ * a row-group kernel. (min, +) and (or, and) results do not depend on the
+ * order of the terms, so they are exact: the same bits as a sequential loop
+ * over each row in the accumulation type. */
 mxe_status mxe_spmv_semiring(mxe_ctx *ctx, mxe_mat m, int32_t semiring, int32_t k, const void *X,
                              int64_t ldx, void *Y, int64_t ldy, uint32_t flags, void *stream);
 

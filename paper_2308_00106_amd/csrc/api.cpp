@@ -845,16 +845,28 @@ mxe_status mxe_spmv(mxe_ctx *ctx, mxe_mat m, int32_t k, const void *X, int64_t l
     return spmv_internal(ctx, *A, k, X, ldx, Y, ldy, flags, (hipStream_t)stream);
 }
 
-// Y = M X over (min, +) or (or, and), 16 columns per launch; for a permuted
-// matrix in the original index space X is gathered by cperm and Y scattered
-// by rperm around the product, as for (+, *).
-static mxe_status semiring_core(Matrix &A, int semiring, int32_t k, const void *X, int64_t ldx,
-                                void *Y, int64_t ldy, hipStream_t s) {
+// Y = M X over (min, +) or (or, and), 16 columns per launch: on the matrix's
+// column-slab layout when its tuned (+, *) variant is one, else the row-group
+// semiring kernel. For a permuted matrix in the original index space X is
+// gathered by cperm and Y scattered by rperm around the product, as for (+, *).
+static mxe_status semiring_core(mxe_ctx *ctx, Matrix &A, int semiring, int32_t k, const void *X,
+                                int64_t ldx, void *Y, int64_t ldy, hipStream_t s) {
     const int eb = elem_bytes_of(A.storage);
     for (int32_t c0 = 0; c0 < k; c0 += 16) {
-        SpmvArgs a = make_args(A, std::min<int32_t>(16, k - c0), (const char *)X + (size_t)c0 * eb,
-                               ldx, (char *)Y + (size_t)c0 * eb, ldy);
-        MXE_HIP(launch_spmv_semiring(a, semiring, s));
+        const int32_t kc = std::min<int32_t>(16, k - c0);
+        const void *Xc = (const char *)X + (size_t)c0 * eb;
+        void *Yc = (char *)Y + (size_t)c0 * eb;
+        TuneResult r;
+        mxe_status st = ensure_variant(ctx, A, kc, s, &r);
+        if (st) return st;
+        if ((r.variant & 0xf00) == MXE_VAR_SLAB) {
+            SpmvArgs a;
+            if ((st = prepare_args(ctx, A, r.variant, kc, Xc, ldx, Yc, ldy, s, &a))) return st;
+            MXE_HIP(launch_spmv_slab(*a.slab, a.vtype, semiring, a.slab_off, a.slab_idx, a.slab_val,
+                                     kc, Xc, ldx, Yc, ldy, s));
+        } else {
+            MXE_HIP(launch_spmv_semiring(make_args(A, kc, Xc, ldx, Yc, ldy), semiring, s));
+        }
     }
     return MXE_OK;
 }
@@ -874,13 +886,13 @@ mxe_status mxe_spmv_semiring(mxe_ctx *ctx, mxe_mat m, int32_t semiring, int32_t 
     if (st) return st;
     hipStream_t s = (hipStream_t)stream;
     if (!(flags & MXE_SPACE_ORIGINAL) || !A->rperm)
-        return semiring_core(*A, semiring, k, X, ldx, Y, ldy, s);
+        return semiring_core(ctx, *A, semiring, k, X, ldx, Y, ldy, s);
     const int eb = elem_bytes_of(A->storage);
     Scratch xp, yp;
     if ((st = xp.alloc((size_t)eb * std::max(A->ncols, 1) * k, s))) return st;
     if ((st = yp.alloc((size_t)eb * std::max(A->nrows, 1) * k, s))) return st;
     MXE_HIP(launch_gather_rows(A->ncols, k, A->cperm, X, ldx, xp.p, k, eb, s));
-    if ((st = semiring_core(*A, semiring, k, xp.p, k, yp.p, k, s))) return st;
+    if ((st = semiring_core(ctx, *A, semiring, k, xp.p, k, yp.p, k, s))) return st;
     MXE_HIP(launch_scatter_rows(A->nrows, k, A->rperm, yp.p, k, Y, ldy, eb, s));
     return MXE_OK;
 }

@@ -150,6 +150,27 @@ __device__ inline float bf16_to_f32(uint16_t b) {
     return __uint_as_float((uint32_t)b << 16);
 }
 
+// Semirings of the product (MXE_SR_* in mxe.h: 0 (+, *), 1 (min, +), 2 (or,
+// and)), Section 2: identity of the sum, the product of a value and an x, the
+// sum. min and or are exact; a min accumulator only ever takes a smaller
+// term, so it never turns NaN.
+template <int SR, typename T> struct Semiring;
+template <typename T> struct Semiring<0, T> {
+    __device__ static T identity() { return T(0); }
+    __device__ static T mul(T a, T x) { return a * x; }
+    __device__ static T add(T p, T q) { return p + q; }
+};
+template <typename T> struct Semiring<1, T> {
+    __device__ static T identity() { return T(__builtin_inf()); }
+    __device__ static T mul(T a, T x) { return a + x; }
+    __device__ static T add(T p, T q) { return q < p ? q : p; }
+};
+template <typename T> struct Semiring<2, T> {
+    __device__ static T identity() { return T(0); }
+    __device__ static T mul(T a, T x) { return (a != T(0) && x != T(0)) ? T(1) : T(0); }
+    __device__ static T add(T p, T q) { return (p != T(0) || q != T(0)) ? T(1) : T(0); }
+};
+
 // Inclusive segmented scan over a wavefront whose keys never decrease
 // (equal keys are adjacent; real keys stay below 0xfffffffe, padding lanes
 // carry 0xffffffff after every real one), on DPP lane moves instead of LDS
@@ -205,6 +226,41 @@ __device__ inline void scan_bcast(uint32_t key, T (&v)[KM]) {
         v[q] += take ? m : T(0);
     }
 }
+// The same scan for an operator other than +: every move, inside a row too,
+// reads the operator's identity and the never-matching key where its source
+// lane lies outside the row (for min, a moved-in 0 would be wrong).
+template <int CTRL, int RMASK, typename Op, typename T, int KM>
+__device__ inline void scan_step_op(uint32_t key, T (&v)[KM]) {
+    const bool take = (uint32_t)__builtin_amdgcn_update_dpp((int)0xfffffffeu, (int)key, CTRL, RMASK,
+                                                            0xf, false) == key;
+#pragma unroll
+    for (int q = 0; q < KM; ++q) {
+        T m;
+        if constexpr (sizeof(T) == 8) {
+            const double id = Op::identity();
+            const int lo = __builtin_amdgcn_update_dpp(__double2loint(id), __double2loint(v[q]), CTRL,
+                                                       RMASK, 0xf, false);
+            const int hi = __builtin_amdgcn_update_dpp(__double2hiint(id), __double2hiint(v[q]), CTRL,
+                                                       RMASK, 0xf, false);
+            m = __hiloint2double(hi, lo);
+        } else {
+            m = __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int((float)Op::identity()),
+                                                           __float_as_int(v[q]), CTRL, RMASK, 0xf,
+                                                           false));
+        }
+        v[q] = take ? Op::add(v[q], m) : v[q];
+    }
+}
+template <typename Op, typename T, int KM>
+__device__ inline void segmented_scan_op(uint32_t key, T (&v)[KM]) {
+    scan_step_op<0x111, 0xf, Op>(key, v);
+    scan_step_op<0x112, 0xf, Op>(key, v);
+    scan_step_op<0x114, 0xf, Op>(key, v);
+    scan_step_op<0x118, 0xf, Op>(key, v);
+    scan_step_op<0x142, 0xa, Op>(key, v);
+    scan_step_op<0x143, 0xc, Op>(key, v);
+}
+
 template <typename T, int KM>
 __device__ inline void segmented_scan(uint32_t key, T (&v)[KM]) {
     scan_shr<0x111>(key, v);            // row_shr:1

@@ -114,9 +114,10 @@ size_t slab_build_ws_bytes(const SlabGeom &g);
 hipError_t launch_slab_build(const SlabGeom &g, const int32_t *rp, const int32_t *col,
                              const void *val, int val_bytes, int32_t *off, uint32_t *idx_out,
                              void *val_out, void *ws, hipStream_t s);
-hipError_t launch_spmv_slab(const SlabGeom &g, int vtype, const int32_t *off, const uint32_t *idx,
-                            const void *val, int32_t k, const void *X, int64_t ldx, void *Y,
-                            int64_t ldy, hipStream_t s);
+// semiring: MXE_SR_* (mxe.h)
+hipError_t launch_spmv_slab(const SlabGeom &g, int vtype, int semiring, const int32_t *off,
+                            const uint32_t *idx, const void *val, int32_t k, const void *X,
+                            int64_t ldx, void *Y, int64_t ldy, hipStream_t s);
 
 struct SpmvArgs {
     int32_t nrows, ncols;

@@ -171,17 +171,18 @@ template <> struct SlabVal<uint16_t, float> {
 // inside a slab a wavefront loads up to Unroll chunks of its group at once,
 // issues their x gathers together, then reduces each chunk by row. The first
 // batch of the next slab's group is loaded before each barrier.
-template <typename V, typename T, int KM>
+template <typename V, typename T, int KM, int SR>
 __global__ __launch_bounds__(kSlabBlock) void k_spmv_slab(SlabGeom g, const int32_t *__restrict__ off,
                                                           const uint32_t *__restrict__ idx,
                                                           const V *__restrict__ val, int32_t k,
                                                           const T *__restrict__ X, int64_t ldx,
                                                           T *__restrict__ Y, int64_t ldy) {
+    using S = Semiring<SR, T>;
     extern __shared__ unsigned char smem[];
     T *yp = reinterpret_cast<T *>(smem);
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     const int32_t R = g.rows_per_block;
-    for (int i = threadIdx.x; i < R * KM; i += kSlabBlock) yp[i] = T(0);
+    for (int i = threadIdx.x; i < R * KM; i += kSlabBlock) yp[i] = S::identity();
     T *ywave = yp + (int64_t)wave * g.rows_per_sub * KM;
     // this wavefront's groups (one per slab) and their offsets, staged in LDS
     __shared__ int32_t soff[kSubBlocks][kSlabMax + 1];
@@ -224,13 +225,15 @@ __global__ __launch_bounds__(kSlabBlock) void k_spmv_slab(SlabGeom g, const int3
                 const uint32_t key = u[j] != 0xffffffffu ? (u[j] >> g.cbits) : 0xffffffffu;
                 T prod[KM];
 #pragma unroll
-                for (int q = 0; q < KM; ++q) prod[q] = a[j] * xv[j][q];
-                segmented_scan<T, KM>(key, prod);
+                for (int q = 0; q < KM; ++q) prod[q] = S::mul(a[j], xv[j][q]);
+                if constexpr (SR == 0) segmented_scan<T, KM>(key, prod);
+                else segmented_scan_op<S, T, KM>(key, prod);
                 const uint32_t nxt = __shfl_down(key, 1);
                 const bool tail = key != 0xffffffffu && (lane == kWave - 1 || nxt != key);
                 if (tail) {
 #pragma unroll
-                    for (int q = 0; q < KM; ++q) ywave[(int64_t)key * KM + q] += prod[q];
+                    for (int q = 0; q < KM; ++q)
+                        ywave[(int64_t)key * KM + q] = S::add(ywave[(int64_t)key * KM + q], prod[q]);
                 }
                 // the next chunk's tails may update the same rows: keep order
                 __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -251,24 +254,36 @@ __global__ __launch_bounds__(kSlabBlock) void k_spmv_slab(SlabGeom g, const int3
     }
 }
 
-template <typename V, typename T, int KM>
+template <typename V, typename T, int KM, int SR>
 hipError_t slab_launch(const SlabGeom &g, const int32_t *off, const uint32_t *idx, const void *val,
                        int32_t k, const void *X, int64_t ldx, void *Y, int64_t ldy, hipStream_t s) {
     const size_t lds = (size_t)g.rows_per_block * KM * sizeof(T);
-    hipLaunchKernelGGL((k_spmv_slab<V, T, KM>), dim3(g.blocks), dim3(kSlabBlock), lds, s, g, off,
+    hipLaunchKernelGGL((k_spmv_slab<V, T, KM, SR>), dim3(g.blocks), dim3(kSlabBlock), lds, s, g, off,
                        idx, (const V *)val, k, (const T *)X, ldx, (T *)Y, ldy);
     return hipGetLastError();
 }
 
-template <typename V, typename T>
+template <typename V, typename T, int SR>
 hipError_t slab_by_k(const SlabGeom &g, const int32_t *off, const uint32_t *idx, const void *val,
                      int32_t k, const void *X, int64_t ldx, void *Y, int64_t ldy, hipStream_t s) {
     switch (g.kclass) {
-    case 1: return slab_launch<V, T, 1>(g, off, idx, val, k, X, ldx, Y, ldy, s);
-    case 2: return slab_launch<V, T, 2>(g, off, idx, val, k, X, ldx, Y, ldy, s);
-    case 4: return slab_launch<V, T, 4>(g, off, idx, val, k, X, ldx, Y, ldy, s);
-    case 8: return slab_launch<V, T, 8>(g, off, idx, val, k, X, ldx, Y, ldy, s);
-    case 16: return slab_launch<V, T, 16>(g, off, idx, val, k, X, ldx, Y, ldy, s);
+    case 1: return slab_launch<V, T, 1, SR>(g, off, idx, val, k, X, ldx, Y, ldy, s);
+    case 2: return slab_launch<V, T, 2, SR>(g, off, idx, val, k, X, ldx, Y, ldy, s);
+    case 4: return slab_launch<V, T, 4, SR>(g, off, idx, val, k, X, ldx, Y, ldy, s);
+    case 8: return slab_launch<V, T, 8, SR>(g, off, idx, val, k, X, ldx, Y, ldy, s);
+    case 16: return slab_launch<V, T, 16, SR>(g, off, idx, val, k, X, ldx, Y, ldy, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename V, typename T>
+hipError_t slab_by_semiring(const SlabGeom &g, int semiring, const int32_t *off, const uint32_t *idx,
+                            const void *val, int32_t k, const void *X, int64_t ldx, void *Y,
+                            int64_t ldy, hipStream_t s) {
+    switch (semiring) {
+    case 0: return slab_by_k<V, T, 0>(g, off, idx, val, k, X, ldx, Y, ldy, s);
+    case 1: return slab_by_k<V, T, 1>(g, off, idx, val, k, X, ldx, Y, ldy, s);
+    case 2: return slab_by_k<V, T, 2>(g, off, idx, val, k, X, ldx, Y, ldy, s);
     default: return hipErrorInvalidValue;
     }
 }
@@ -340,14 +355,14 @@ hipError_t launch_slab_build(const SlabGeom &g, const int32_t *rp, const int32_t
     return hipGetLastError();
 }
 
-hipError_t launch_spmv_slab(const SlabGeom &g, int vtype, const int32_t *off, const uint32_t *idx,
-                            const void *val, int32_t k, const void *X, int64_t ldx, void *Y,
-                            int64_t ldy, hipStream_t s) {
+hipError_t launch_spmv_slab(const SlabGeom &g, int vtype, int semiring, const int32_t *off,
+                            const uint32_t *idx, const void *val, int32_t k, const void *X,
+                            int64_t ldx, void *Y, int64_t ldy, hipStream_t s) {
     if (k > g.kclass) return hipErrorInvalidValue;
     switch (vtype) {
-    case VAL_F64: return slab_by_k<double, double>(g, off, idx, val, k, X, ldx, Y, ldy, s);
-    case VAL_F32: return slab_by_k<float, float>(g, off, idx, val, k, X, ldx, Y, ldy, s);
-    case VAL_BF16: return slab_by_k<uint16_t, float>(g, off, idx, val, k, X, ldx, Y, ldy, s);
+    case VAL_F64: return slab_by_semiring<double, double>(g, semiring, off, idx, val, k, X, ldx, Y, ldy, s);
+    case VAL_F32: return slab_by_semiring<float, float>(g, semiring, off, idx, val, k, X, ldx, Y, ldy, s);
+    case VAL_BF16: return slab_by_semiring<uint16_t, float>(g, semiring, off, idx, val, k, X, ldx, Y, ldy, s);
     default: return hipErrorInvalidValue;
     }
 }

@@ -545,20 +545,9 @@ hipError_t coo_launch(const SpmvArgs &a, hipStream_t s) {
 
 // ---- other semirings (Section 2) --------------------------------------------------
 // L lanes per row take its entries in a lane stride and combine them with the
-// semiring's product, then an xor butterfly over the L lanes with its sum.
-// min and or are exact, so the order of the terms does not matter.
-
-template <int SR, typename T> struct Semiring;
-template <typename T> struct Semiring<MXE_SR_MIN_PLUS, T> {
-    __device__ static T zero() { return T(__builtin_inf()); }
-    __device__ static T mul(T a, T x) { return a + x; }
-    __device__ static T add(T p, T q) { return q < p ? q : p; }   // never NaN: see the header
-};
-template <typename T> struct Semiring<MXE_SR_OR_AND, T> {
-    __device__ static T zero() { return T(0); }
-    __device__ static T mul(T a, T x) { return (a != T(0) && x != T(0)) ? T(1) : T(0); }
-    __device__ static T add(T p, T q) { return (p != T(0) || q != T(0)) ? T(1) : T(0); }
-};
+// semiring's product, then an xor butterfly over the L lanes with its sum
+// (Semiring in device_common.h). min and or are exact, so the order of the
+// terms does not matter.
 
 template <typename V, typename T, int SR, int L, int KM>
 __global__ __launch_bounds__(kBlock) void k_spmv_semiring(int32_t nrows, const int32_t *__restrict__ rp,
@@ -572,7 +561,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_semiring(int32_t nrows, const i
     const int lane = (int)(gt % L);
     T acc[KM];
 #pragma unroll
-    for (int q = 0; q < KM; ++q) acc[q] = S::zero();
+    for (int q = 0; q < KM; ++q) acc[q] = S::identity();
     if (row < nrows) {                       // other lanes still join the butterfly
         for (int32_t p = rp[row] + lane; p < rp[row + 1]; p += L) {
             const T a = ValLoad<V, T>::get(val + p);
@@ -787,8 +776,8 @@ hipError_t launch_spmv(const SpmvArgs &a, int variant, hipStream_t s) {
     if (a.nrows <= 0) return hipSuccess;
     if ((variant & 0xf00) == MXE_VAR_SLAB) {
         if (!a.slab) return hipErrorInvalidValue;
-        return launch_spmv_slab(*a.slab, a.vtype, a.slab_off, a.slab_idx, a.slab_val, a.k, a.X,
-                                a.ldx, a.Y, a.ldy, s);
+        return launch_spmv_slab(*a.slab, a.vtype, MXE_SR_PLUS_TIMES, a.slab_off, a.slab_idx,
+                                a.slab_val, a.k, a.X, a.ldx, a.Y, a.ldy, s);
     }
     switch (a.vtype) {
     case VAL_F64: return spmv_t<double, double>(a, variant, s);

@@ -452,14 +452,18 @@ def test_semiring_products_bit_exact(ctx, name, make, k):
     rperm, cperm = ctx.get_permutation(B)
     Bo = synth.CSR(A0.nrows, A0.ncols, *oracle.permute_csr(A0, rperm, cperm))
     shape = (A0.nrows, k) if k > 1 else (A0.nrows,)
-    for sr in (mx.SR_MIN_PLUS, mx.SR_OR_AND):
-        for H, Ho, flags, Xin in ((A, A0, 0, X), (B, Bo, 0, X[cperm]),
-                                  (B, A0, mx.SPACE_ORIGINAL, X)):
-            Y = torch.full(shape, float("nan"), dtype=torch.float64, device="cuda")
-            ctx.spmv_semiring(H, sr, torch_vec(Xin, torch.float64), Y, flags=flags)
-            torch.cuda.synchronize()
-            ref = oracle.spmm_semiring(sr, Ho.nrows, Ho.row_ptr, Ho.col, Ho.val, Xin)
-            assert np.array_equal(Y.cpu().numpy(), ref.reshape(shape)), (name, sr, flags)
+    # the tuned kernel, then the column-slab kernel forced (64 KiB and 2 MiB slabs)
+    for v in (None, mx.variant(mx.VAR_SLAB, 1), mx.variant(mx.VAR_SLAB, 32)):
+        if v is not None and not (_force(ctx, A, k, v) and _force(ctx, B, k, v)):
+            continue
+        for sr in (mx.SR_MIN_PLUS, mx.SR_OR_AND):
+            for H, Ho, flags, Xin in ((A, A0, 0, X), (B, Bo, 0, X[cperm]),
+                                      (B, A0, mx.SPACE_ORIGINAL, X)):
+                Y = torch.full(shape, float("nan"), dtype=torch.float64, device="cuda")
+                ctx.spmv_semiring(H, sr, torch_vec(Xin, torch.float64), Y, flags=flags)
+                torch.cuda.synchronize()
+                ref = oracle.spmm_semiring(sr, Ho.nrows, Ho.row_ptr, Ho.col, Ho.val, Xin)
+                assert np.array_equal(Y.cpu().numpy(), ref.reshape(shape)), (name, sr, flags, v)
     ctx.release(B)
     ctx.release(A)
 
@@ -471,6 +475,7 @@ def test_semiring_products_reduced_storage(ctx, storage):
     X32 = X.astype(np.float32).astype(np.float64)
     A = ctx.register(A0, storage)
     vals = oracle.stored_values(A0.val, storage)
+    ctx.set_variant(A, 4, mx.variant(mx.VAR_SLAB, 4))             # the column-slab kernel
     for sr in (mx.SR_MIN_PLUS, mx.SR_OR_AND):
         Y = torch.full((A0.nrows, 4), float("nan"), dtype=torch.float32, device="cuda")
         ctx.spmv_semiring(A, sr, torch_vec(X, torch.float32), Y)
