@@ -113,6 +113,38 @@ def test_batch_plan_graph_replays(ctx):
     ctx.batch_destroy(plan)
 
 
+def test_batch_mixed_storage(ctx):
+    """FP64, FP32 and BF16 items in one persistent launch (the instance that
+    carries every value type), directly and from a graph replay."""
+    mats = _pool(6, 400)
+    storages = ["f64", "f32", "bf16", "f64", "bf16", "f32"]
+    ks = [1, 4, 2, 16, 3, 8]
+    handles = [ctx.permute(ctx.register(A, st), 11) for A, st in zip(mats, storages)]
+    B0 = []
+    for H, A in zip(handles, mats):
+        rperm, cperm = ctx.get_permutation(H)
+        B0.append(synth.CSR(A.nrows, A.ncols, *oracle.permute_csr(A, rperm, cperm)))
+    Xs = [_rand_x(A, k, 60 + i) for i, (A, k) in enumerate(zip(mats, ks))]
+    dts = [torch.float64 if st == "f64" else torch.float32 for st in storages]
+    Xt = [torch_vec(X, dt) for X, dt in zip(Xs, dts)]
+    Ys = [torch.full((A.nrows, k) if k > 1 else (A.nrows,), float("nan"), dtype=dt, device="cuda")
+          for A, k, dt in zip(mats, ks, dts)]
+    ctx.spmv_batch(list(zip(handles, Xt, Ys)))
+    torch.cuda.synchronize()
+    for Bo, X, Y, st in zip(B0, Xs, Ys, storages):
+        assert spmv_error(Bo, X, Y.cpu().numpy().astype(np.float64), st) <= TOL[st], st
+    plan = ctx.batch_create(list(zip(handles, Xt, Ys)))
+    for Y in Ys:
+        Y.fill_(float("nan"))
+    ctx.batch_launch(plan)
+    torch.cuda.synchronize()
+    for Bo, X, Y, st in zip(B0, Xs, Ys, storages):
+        assert spmv_error(Bo, X, Y.cpu().numpy().astype(np.float64), st) <= TOL[st], st
+    ctx.batch_destroy(plan)
+    for H in handles:
+        ctx.release(H)
+
+
 # --- serving ---------------------------------------------------------------------------
 
 def test_serving_mix_matches_alone(ctx):
