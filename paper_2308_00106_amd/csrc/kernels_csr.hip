@@ -7,10 +7,10 @@
 // indices by the top 10-12 key bits (per-workgroup LDS histograms, a scan,
 // an LDS-cursor scatter of 4-byte indices) and one workgroup per bucket of
 // ~2K sorts it in LDS (split by the next 8 bits, then a rank by (key, index)
-// inside sub-buckets of ~8). Larger ranges take a global bucket path (device
-// atomics, buckets of ~30 ranked by one wavefront each). Either way two light
-// passes over 4-byte indices replace the eight read-write passes of an LSD
-// radix sort over 12-byte (key, index) pairs.
+// inside sub-buckets of ~8). Larger ranges bucket by up to 20 top bits with
+// device atomics instead of LDS histograms and sort the buckets the same way.
+// Either way two light passes over 4-byte indices replace the eight read-write
+// passes of an LSD radix sort over 12-byte (key, index) pairs.
 #include "device_common.h"
 #include "internal.h"
 
@@ -128,11 +128,11 @@ __global__ __launch_bounds__(kBlock) void k_scan_tiles(const int32_t *in, int32_
     }
 }
 
-// ---- random permutation: global bucket path (above 8.4M indices) -------------
+// ---- random permutation: global bucketing (above 8.4M indices) ---------------
 
-inline int bucket_bits(int64_t n) {
+inline int bucket_bits(int64_t n) {          // mean bucket <= 2048 up to 2^31 indices
     int b = 0;
-    while (b < 20 && (n >> b) > 48) ++b;     // mean bucket size in (24, 48]
+    while (b < 20 && (n >> b) > 2048) ++b;
     return b;
 }
 
@@ -156,46 +156,6 @@ __global__ __launch_bounds__(kBlock) void k_bucket_scatter(int64_t n, uint64_t s
          i += (int64_t)gridDim.x * blockDim.x) {
         uint32_t b = bucket_of(sm64_key(seed, (uint64_t)i), bits);
         items[offsets[b] + slot[i]] = (int32_t)i;
-    }
-}
-
-__device__ inline uint64_t readlane_u64(uint64_t v, int lane) {
-    uint32_t lo = __builtin_amdgcn_readlane((int)(uint32_t)v, lane);
-    uint32_t hi = __builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), lane);
-    return ((uint64_t)hi << 32) | lo;
-}
-
-// One wavefront per bucket: each item's final position is the bucket offset
-// plus the number of bucket items ordered before it by (key, index).
-__global__ __launch_bounds__(kBlock) void k_bucket_rank(int64_t nbuckets, uint64_t seed,
-                                                        const int32_t *offsets,
-                                                        const int32_t *items, int32_t *perm,
-                                                        int32_t *inv) {
-    const int lane = threadIdx.x & (kWave - 1);
-    int64_t bucket = (int64_t)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave;
-    if (bucket >= nbuckets) return;                      // uniform per wavefront
-    const int32_t o = offsets[bucket];
-    const int32_t m = offsets[bucket + 1] - o;
-    for (int32_t c0 = 0; c0 < m; c0 += kWave) {
-        const bool valid = c0 + lane < m;
-        const int32_t idx = valid ? items[o + c0 + lane] : 0x7fffffff;
-        const uint64_t key = valid ? sm64_key(seed, (uint64_t)idx) : ~0ull;
-        int32_t rank = 0;
-        for (int32_t d0 = 0; d0 < m; d0 += kWave) {
-            const bool ov = d0 + lane < m;
-            const int32_t oidx = ov ? items[o + d0 + lane] : 0;
-            const uint64_t okey = ov ? sm64_key(seed, (uint64_t)oidx) : 0;
-            const int cnt = min(kWave, m - d0);
-            for (int j = 0; j < cnt; ++j) {
-                uint64_t kj = readlane_u64(okey, j);
-                int32_t ij = __builtin_amdgcn_readlane(oidx, j);
-                rank += (kj < key) | ((kj == key) & (ij < idx));
-            }
-        }
-        if (valid) {
-            perm[o + rank] = idx;
-            if (inv) inv[idx] = o + rank;
-        }
     }
 }
 
@@ -263,7 +223,8 @@ __device__ inline bool key_less(uint64_t ka, int32_t ia, uint64_t kb, int32_t ib
 // start of its sub-bucket + its rank by (key, index) inside the sub-bucket.
 // A bucket above kBucketCap (not expected from uniform keys) is ranked
 // against the whole bucket in memory instead.
-__global__ __launch_bounds__(kBlock) void k_perm_bucket_sort(int32_t nd, int32_t nwg, uint64_t seed,
+// Bucket d spans items [offsets[d * stride], offsets[(d + 1) * stride]).
+__global__ __launch_bounds__(kBlock) void k_perm_bucket_sort(int32_t nd, int32_t stride, uint64_t seed,
                                                              int bits, const int32_t *offsets,
                                                              const int32_t *items, int32_t *perm,
                                                              int32_t *inv) {
@@ -273,8 +234,8 @@ __global__ __launch_bounds__(kBlock) void k_perm_bucket_sort(int32_t nd, int32_t
     __shared__ int32_t cursor[kBlock];
     __shared__ int32_t wsum[kBlock / kWave];
     const int32_t d = blockIdx.x;
-    const int32_t o = offsets[(int64_t)d * nwg];
-    const int32_t m = offsets[(int64_t)(d + 1) * nwg] - o;   // the scan's last entry is n
+    const int32_t o = offsets[(int64_t)d * stride];
+    const int32_t m = offsets[(int64_t)(d + 1) * stride] - o;   // the scan's last entry is n
     if (m > kBucketCap) {
         for (int32_t t = threadIdx.x; t < m; t += kBlock) {
             const int32_t idx = items[o + t];
@@ -674,8 +635,8 @@ hipError_t launch_random_perm(int64_t n, uint64_t stream_seed, int32_t *perm, in
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_bucket_scatter, dim3(g), dim3(kBlock), 0, s, n, stream_seed, bits,
                        (const int32_t *)counts, (const int32_t *)slot, items);
-    hipLaunchKernelGGL(k_bucket_rank, dim3(cdiv(nb, kBlock / kWave)), dim3(kBlock), 0, s, nb,
-                       stream_seed, (const int32_t *)counts, (const int32_t *)items, perm, inv);
+    hipLaunchKernelGGL(k_perm_bucket_sort, dim3((unsigned)nb), dim3(kBlock), 0, s, (int32_t)nb, 1,
+                       stream_seed, bits, (const int32_t *)counts, (const int32_t *)items, perm, inv);
     return hipGetLastError();
 }
 

@@ -50,9 +50,10 @@ def test_permutation_matches_oracle(ctx, n):
 
 
 @pytest.mark.slow
-def test_permutation_large_n_bucket_path(ctx):
-    """Above 2048 << 12 indices the permutation takes its global bucket path."""
-    n = 9_000_000
+@pytest.mark.parametrize("n", [9_000_000, 40_000_000])
+def test_permutation_large_n_bucket_path(ctx, n):
+    """Above 2048 << 12 indices the permutation buckets with device atomics
+    (up to 2^20 buckets of ~2K) before the same per-bucket LDS sort."""
     A = ctx.register(_diag(n, 7))
     B = ctx.permute(A, 5, mx.ROWS)
     rp, _ = ctx.get_permutation(B)
