@@ -275,7 +275,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_merge(
     // inclusive segmented scan of the carries over threads with equal key
     for (int off = 1; off < kBlock; off <<= 1) {
         T v[KM];
-        const bool take = threadIdx.x >= off && key[threadIdx.x - off] == key[threadIdx.x];
+        const bool take = (int)threadIdx.x >= off && key[threadIdx.x - off] == key[threadIdx.x];
 #pragma unroll
         for (int q = 0; q < KM; ++q) v[q] = take ? part[threadIdx.x - off][q] : T(0);
         __syncthreads();
