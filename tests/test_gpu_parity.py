@@ -261,6 +261,28 @@ def test_identity_original_space(ctx):
     ctx.release(A)
 
 
+@pytest.mark.parametrize("k", [1, 5])
+def test_every_variant_is_bitwise_repeatable(ctx, k):
+    """Each variant sums every row in a fixed order: two runs give the same bits."""
+    A0 = synth.config3(1, n=60_000)
+    A = ctx.register(A0)
+    B = ctx.permute(A, 4)
+    X = torch_vec(synth.vector(A0.ncols, 2, k=k), torch.float64)
+    for v in VARIANTS + [mx.variant(mx.VAR_SLAB, 12)]:
+        if not _force(ctx, B, k, v):
+            continue
+        outs = []
+        for _ in range(2):
+            Y = torch.empty((A0.nrows, k) if k > 1 else (A0.nrows,), dtype=torch.float64,
+                            device="cuda")
+            ctx.spmv(B, X, Y)
+            torch.cuda.synchronize()
+            outs.append(Y.cpu().numpy().view(np.uint64).copy())
+        assert np.array_equal(outs[0], outs[1]), hex(v)
+    ctx.release(B)
+    ctx.release(A)
+
+
 def test_runs_are_bitwise_deterministic(ctx):
     A0 = synth.config3(1, n=40_000)
     A = ctx.register(A0)
