@@ -176,7 +176,8 @@ __global__ __launch_bounds__(kSlabBlock) void k_spmv_slab(SlabGeom g, const int3
                                                           const uint32_t *__restrict__ idx,
                                                           const V *__restrict__ val, int32_t k,
                                                           const T *__restrict__ X, int64_t ldx,
-                                                          T *__restrict__ Y, int64_t ldy) {
+                                                          T *__restrict__ Y, int64_t ldy,
+                                                          int vec_x) {
     using S = Semiring<SR, T>;
     extern __shared__ unsigned char smem[];
     T *yp = reinterpret_cast<T *>(smem);
@@ -215,6 +216,19 @@ __global__ __launch_bounds__(kSlabBlock) void k_spmv_slab(SlabGeom g, const int3
             for (int j = 0; j < kD; ++j) {
                 const bool v = u[j] != 0xffffffffu;
                 const T *xr = X + (int64_t)(v ? (u[j] & cmask) : 0) * ldx;
+                if constexpr (KM > 1) {
+                    if (vec_x) {                              // k == KM, 16-byte aligned rows
+                        constexpr int W = (16 / (int)sizeof(T)) < KM ? 16 / (int)sizeof(T) : KM;
+                        typedef T vec_t __attribute__((ext_vector_type(W)));
+#pragma unroll
+                        for (int q = 0; q < KM; q += W) {
+                            const vec_t w = *reinterpret_cast<const vec_t *>(xr + q);
+#pragma unroll
+                            for (int r = 0; r < W; ++r) xv[j][q + r] = v ? w[r] : T(0);
+                        }
+                        continue;
+                    }
+                }
 #pragma unroll
                 for (int q = 0; q < KM; ++q) xv[j][q] = (v && (KM == 1 || q < k)) ? xr[q] : T(0);
             }
@@ -258,8 +272,12 @@ template <typename V, typename T, int KM, int SR>
 hipError_t slab_launch(const SlabGeom &g, const int32_t *off, const uint32_t *idx, const void *val,
                        int32_t k, const void *X, int64_t ldx, void *Y, int64_t ldy, hipStream_t s) {
     const size_t lds = (size_t)g.rows_per_block * KM * sizeof(T);
+    // whole X rows as 16-byte vector loads when each row is exactly KM values
+    // on a 16-byte boundary: never a read past a row's k values
+    const int vec_x = KM > 1 && k == KM && (ldx * sizeof(T)) % 16 == 0 &&
+                      (reinterpret_cast<uintptr_t>(X) % 16) == 0;
     hipLaunchKernelGGL((k_spmv_slab<V, T, KM, SR>), dim3(g.blocks), dim3(kSlabBlock), lds, s, g, off,
-                       idx, (const V *)val, k, (const T *)X, ldx, (T *)Y, ldy);
+                       idx, (const V *)val, k, (const T *)X, ldx, (T *)Y, ldy, vec_x);
     return hipGetLastError();
 }
 
