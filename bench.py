@@ -40,13 +40,14 @@ def spmv_bytes(nrows, ncols, nnz, val_bytes, vec_bytes, k=1):
 
 def kernel_source_hash(variant_hex: str = "0x300") -> str:
     """Hash of the sources the measured SpMV kernel is built from: its kernel
-    file (column-slab or row kernels), the shared device helpers and, for the
-    slab kernel, its layout descriptor."""
+    file and device body (column-slab or row kernels), the shared device
+    helpers and, for the slab kernel, its layout descriptor."""
     import re
     csrc = os.path.join(ROOT, "paper_2308_00106_amd", "csrc")
     slab = (int(variant_hex, 16) & 0xf00) == 0x300
     h = hashlib.sha256()
-    for f in ("kernels_slab.hip" if slab else "kernels_spmv.hip", "device_common.h"):
+    files = ("kernels_slab.hip", "slab_device.h") if slab else ("kernels_spmv.hip", "spmv_device.h")
+    for f in (*files, "device_common.h"):
         with open(os.path.join(csrc, f), "rb") as fh:
             h.update(fh.read())
     if slab:

@@ -1017,6 +1017,11 @@ mxe_status mxe_set_variant(mxe_ctx *ctx, mxe_mat m, int32_t k, int32_t variant) 
 
 // ---- batches ------------------------------------------------------------------------
 
+// work units of one batch item: its slab layout's blocks, or row tiles
+static int64_t batch_units(const BatchDesc &d) {
+    return d.slab_off ? d.slab.blocks : (d.nrows + d.rows_per_tile - 1) / d.rows_per_tile;
+}
+
 // Deals the matrices to the per-XCD queues: largest first (bytes one product
 // moves) onto the least loaded queue, so each XCD's share is balanced and its
 // matrices' x stays in its own L2. Each queue lists its matrices in item
@@ -1041,7 +1046,7 @@ static void assign_queues(std::vector<BatchDesc> &descs, const std::vector<uint6
         for (int32_t i = 0; i < n; ++i) {
             if (queue_of[i] != q) continue;
             descs[i].tile_begin = (int32_t)tiles;
-            tiles += (descs[i].nrows + descs[i].rows_per_tile - 1) / descs[i].rows_per_tile;
+            tiles += batch_units(descs[i]);
             qent.push_back(i);
         }
         qs.qtiles[q] = (int32_t)tiles;
@@ -1049,11 +1054,16 @@ static void assign_queues(std::vector<BatchDesc> &descs, const std::vector<uint6
     qs.qbegin[kBatchQueues] = (int32_t)qent.size();
 }
 
+// One desc per item. An item whose tuned variant is the column-slab kernel
+// runs as the blocks of that layout, any other as row tiles with its tuned
+// GROUP lane count. lds: the dynamic LDS the launch needs (the largest slab
+// block's partial y).
 static mxe_status build_descs(mxe_ctx *ctx, int32_t count, const mxe_item *items, hipStream_t s,
                               std::vector<BatchDesc> &descs, std::vector<int32_t> &qent,
-                              BatchQueues &qs) {
+                              BatchQueues &qs, size_t *lds) {
     if (count < 1 || !items) return fail(MXE_ERR_INVALID_ARG, "empty batch");
     descs.clear();
+    *lds = 0;
     std::vector<uint64_t> cost;
     int64_t tiles = 0;
     for (int32_t i = 0; i < count; ++i) {
@@ -1080,8 +1090,19 @@ static mxe_status build_descs(mxe_ctx *ctx, int32_t count, const mxe_item *items
         d.vtype = vtype_of(A->storage);
         d.kclass = kclass_of(it.k);
         d.lanes = std::max(r.group_lanes, d.kclass);   // set_variant may force fewer
-        d.rows_per_tile = (256 / r.group_lanes) * 4;
-        tiles += (A->nrows + d.rows_per_tile - 1) / d.rows_per_tile;
+        d.rows_per_tile = (kBatchBlock / d.lanes) * 2;
+        if ((r.variant & 0xf00) == MXE_VAR_SLAB) {
+            const Matrix::Slab *sl;
+            if ((st = ensure_slab(ctx, *A, d.kclass, r.variant & 0xff, s, &sl))) return st;
+            const int eb = elem_bytes_of(A->storage);
+            d.slab = sl->g;
+            d.slab_off = sl->off;
+            d.slab_idx = sl->idx;
+            d.slab_val = sl->val;
+            d.vec_x = slab_vec_x(d.kclass, it.k, it.X, it.ldx, eb) ? 1 : 0;
+            *lds = std::max(*lds, (size_t)sl->g.rows_per_block * d.kclass * eb);
+        }
+        tiles += batch_units(d);
         if (tiles > INT32_MAX) return fail(MXE_ERR_UNSUPPORTED, "too many tiles in batch");
         descs.push_back(d);
         cost.push_back(request_bytes(*A, it.k));
@@ -1105,8 +1126,12 @@ mxe_status mxe_spmv_batch(mxe_ctx *ctx, int32_t count, const mxe_item *items, vo
     std::vector<BatchDesc> descs;
     std::vector<int32_t> qent;
     BatchQueues qs{};
-    mxe_status st = build_descs(ctx, count, items, s, descs, qent, qs);
+    size_t lds = 0;
+    mxe_status st = build_descs(ctx, count, items, s, descs, qent, qs, &lds);
     if (st) return st;
+    const int vt = common_vtype(descs);
+    const int32_t grid = batch_grid_size(vt, lds);
+    if (grid < 1) return fail(MXE_ERR_DEVICE, "batch kernel occupancy query failed");
     Scratch dd, ctr;
     if ((st = dd.alloc(sizeof(BatchDesc) * descs.size(), s))) return st;
     if ((st = ctr.alloc(sizeof(int32_t) * (kBatchQueues + qent.size()), s))) return st;
@@ -1116,8 +1141,8 @@ mxe_status mxe_spmv_batch(mxe_ctx *ctx, int32_t count, const mxe_item *items, vo
     MXE_HIP(hipMemcpy(counters + kBatchQueues, qent.data(), sizeof(int32_t) * qent.size(),
                       hipMemcpyHostToDevice));
     MXE_HIP(launch_batch_reset(counters, s));
-    MXE_HIP(launch_spmv_batch((const BatchDesc *)dd.p, counters + kBatchQueues, qs, counters,
-                              batch_grid_size(), common_vtype(descs), s));
+    MXE_HIP(launch_spmv_batch((const BatchDesc *)dd.p, counters + kBatchQueues, qs, counters, grid,
+                              lds, vt, s));
     return MXE_OK;
 }
 
@@ -1126,8 +1151,12 @@ mxe_status mxe_batch_create(mxe_ctx *ctx, int32_t count, const mxe_item *items, 
     std::lock_guard<std::recursive_mutex> lk(ctx->mu);
     DeviceGuard g(ctx->device);
     auto plan = std::make_unique<Plan>();
-    mxe_status st = build_descs(ctx, count, items, nullptr, plan->descs, plan->qent, plan->queues);
+    mxe_status st = build_descs(ctx, count, items, nullptr, plan->descs, plan->qent, plan->queues,
+                                &plan->lds);
     if (st) return st;
+    plan->vtype = common_vtype(plan->descs);
+    plan->grid = batch_grid_size(plan->vtype, plan->lds);
+    if (plan->grid < 1) return fail(MXE_ERR_DEVICE, "batch kernel occupancy query failed");
     plan->items.assign(items, items + count);
     MXE_HIP(hipMalloc(&plan->descs_dev, sizeof(BatchDesc) * plan->descs.size()));
     MXE_HIP(hipMalloc(&plan->counters, sizeof(int32_t) * (kBatchQueues + plan->qent.size())));
@@ -1140,7 +1169,7 @@ mxe_status mxe_batch_create(mxe_ctx *ctx, int32_t count, const mxe_item *items, 
     MXE_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
     hipError_t e1 = launch_batch_reset(plan->counters, cs);
     hipError_t e2 = launch_spmv_batch(plan->descs_dev, plan->counters + kBatchQueues, plan->queues,
-                                      plan->counters, batch_grid_size(), common_vtype(plan->descs), cs);
+                                      plan->counters, plan->grid, plan->lds, plan->vtype, cs);
     hipError_t e3 = hipStreamEndCapture(cs, &plan->graph);
     if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) {
         Plan &p = *plan;
@@ -1184,6 +1213,8 @@ mxe_status mxe_batch_launch(mxe_ctx *ctx, mxe_plan h, const mxe_item *items, voi
                 d.Y = items[i].Y;
                 d.ldx = items[i].ldx;
                 d.ldy = items[i].ldy;
+                if (d.slab_off)
+                    d.vec_x = slab_vec_x(d.kclass, d.k, d.X, d.ldx, d.vtype == VAL_F64 ? 8 : 4) ? 1 : 0;
                 changed = true;
             }
             p.items[i] = items[i];

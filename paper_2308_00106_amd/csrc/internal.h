@@ -114,6 +114,13 @@ size_t slab_build_ws_bytes(const SlabGeom &g);
 hipError_t launch_slab_build(const SlabGeom &g, const int32_t *rp, const int32_t *col,
                              const void *val, int val_bytes, int32_t *off, uint32_t *idx_out,
                              void *val_out, void *ws, hipStream_t s);
+// Whole X rows may be read as 16-byte vectors when each row is exactly kclass
+// values (elem_bytes each) on a 16-byte boundary: never a read past a row's k
+// values.
+inline bool slab_vec_x(int kclass, int32_t k, const void *X, int64_t ldx, int elem_bytes) {
+    return kclass > 1 && k == kclass && (ldx * elem_bytes) % 16 == 0 &&
+           (reinterpret_cast<uintptr_t>(X) % 16) == 0;
+}
 // semiring: MXE_SR_* (mxe.h)
 hipError_t launch_spmv_slab(const SlabGeom &g, int vtype, int semiring, const int32_t *off,
                             const uint32_t *idx, const void *val, int32_t k, const void *X,
@@ -161,26 +168,39 @@ struct BatchDesc {             // one matrix of a batch (device-resident table)
     void *Y;
     int64_t ldx, ldy;
     int32_t nrows, k;
-    int32_t vtype, lanes;      // lanes per row (1..64), >= kclass
-    int32_t kclass;            // k rounded up to a power of two (column lanes)
-    int32_t rows_per_tile;     // rows one work item covers
-    int32_t tile_begin;        // first tile index of this matrix within its queue
+    int32_t vtype;             // ValType
+    int32_t kclass;            // k rounded up to a power of two
+    int32_t lanes;             // row tiles: lanes per row (1..64), >= kclass
+    int32_t rows_per_tile;     // row tiles: rows one work unit covers
+    int32_t tile_begin;        // first work unit of this matrix within its queue
+    int32_t vec_x;             // slab units: whole X rows as 16-byte loads (slab_vec_x)
+    // slab units (slab_off non-null): one work unit per block of this layout
+    // for k class kclass, in place of row tiles
+    SlabGeom slab;
+    const int32_t *slab_off;
+    const uint32_t *slab_idx;
+    const void *slab_val;
 };
 // One work queue per XCD: queue q holds the matrices qent[qbegin[q] ..
-// qbegin[q+1]) (indices into the desc table, in tile order) and qtiles[q]
-// tiles in all.
+// qbegin[q+1]) (indices into the desc table, in unit order) and qtiles[q]
+// work units in all.
 constexpr int kBatchQueues = 8;
 struct BatchQueues {
     int32_t qbegin[kBatchQueues + 1];
     int32_t qtiles[kBatchQueues];
 };
+constexpr int kBatchBlock = 1024;       // threads per workgroup of the batch kernel
 // counters: kBatchQueues device ints zeroed by launch_batch_reset before each
 // launch.
 hipError_t launch_batch_reset(int32_t *counters, hipStream_t s);
-// vtype: the ValType every item shares, or -1 for a mixed batch.
+// Workgroups of the batch kernel resident at once on the current device for
+// vtype (a ValType, or -1 for a mixed batch) and lds_bytes of dynamic LDS (the
+// largest slab block's partial y); 0 when the query fails. Not a stream
+// operation: call it before a graph capture.
+int32_t batch_grid_size(int vtype, size_t lds_bytes);
 hipError_t launch_spmv_batch(const BatchDesc *descs, const int32_t *qent, const BatchQueues &queues,
-                             int32_t *counters, int32_t grid, int vtype, hipStream_t s);
-int32_t batch_grid_size();
+                             int32_t *counters, int32_t grid, size_t lds_bytes, int vtype,
+                             hipStream_t s);
 
 // ---- random-gather rate probe -------------------------------------------------
 // ws: probe_gather_ws_bytes; the table is ws's first table_bytes (8-byte

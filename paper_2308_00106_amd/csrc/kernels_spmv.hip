@@ -25,8 +25,7 @@
 //          row with a segmented scan, write whole rows directly and hand the
 //          rows cut by a tile edge to a fix-up pass in tile order.
 // Every variant sums each row in a fixed order, so results are deterministic.
-#include "device_common.h"
-#include "internal.h"
+#include "spmv_device.h"
 #include "../../include/mxe.h"
 
 #include <algorithm>
@@ -39,20 +38,6 @@ constexpr int kBlock = 256;
 constexpr int32_t kFixedParts = 256 * 8;     // FIXED: one part per resident workgroup slot
 
 inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
-
-template <typename P>
-__device__ inline P ld_stream(const P *p) { return __builtin_nontemporal_load(p); }
-
-template <typename V, typename T> struct ValLoad;
-template <> struct ValLoad<double, double> {
-    __device__ static double get(const double *p) { return ld_stream(p); }
-};
-template <> struct ValLoad<float, float> {
-    __device__ static float get(const float *p) { return ld_stream(p); }
-};
-template <> struct ValLoad<uint16_t, float> {
-    __device__ static float get(const uint16_t *p) { return bf16_to_f32(ld_stream(p)); }
-};
 
 // Accumulate the entries of one row handled by this lane (lane, lane + L, ...),
 // then reduce over the group of L lanes with xor butterflies: every lane ends
@@ -337,49 +322,6 @@ __global__ __launch_bounds__(kBlock) void k_merge_fixup(int32_t ntiles, const Ca
     (void)s;
 }
 
-// ---- batched persistent kernel -------------------------------------------------------
-
-// One tile of a batch item with the lane count L and column count KM as
-// runtime values (KM = the item's k class, L >= KM, both powers of two): the
-// column-lane product above, one code path for every item, so the persistent
-// kernel needs the registers of a single accumulator. Groups are L-aligned, so
-// xor shuffles below L stay inside a group.
-template <typename V, typename T>
-__device__ inline void rows_runtime(const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
-                                    const V *__restrict__ val, int32_t k, const T *__restrict__ X,
-                                    int64_t ldx, T *__restrict__ Y, int64_t ldy, int L, int KM,
-                                    int32_t r0, int32_t r1) {
-    const int E = L / KM;
-    const int lane = threadIdx.x % L, q = lane % KM, el = lane / KM;
-    const bool active = q < k;
-    for (int32_t row = r0 + threadIdx.x / L; row < r1; row += kBlock / L) {
-        const int32_t s = ld_stream(rp + row), e = ld_stream(rp + row + 1);
-        T acc = T(0);
-        int32_t p = s + el;
-        for (; p + E < e; p += 2 * E) {
-            const int32_t c0 = ld_stream(col + p), c1 = ld_stream(col + p + E);
-            const T a0 = ValLoad<V, T>::get(val + p), a1 = ValLoad<V, T>::get(val + p + E);
-            const T x0 = active ? X[(int64_t)c0 * ldx + q] : T(0);
-            const T x1 = active ? X[(int64_t)c1 * ldx + q] : T(0);
-            acc += a0 * x0;
-            acc += a1 * x1;
-        }
-        if (p < e) {
-            const int32_t c0 = ld_stream(col + p);
-            const T a0 = ValLoad<V, T>::get(val + p);
-            acc += a0 * (active ? X[(int64_t)c0 * ldx + q] : T(0));
-        }
-        for (int off = L / 2; off >= KM; off >>= 1) acc += __shfl_xor(acc, off);
-        if (el == 0 && active) Y[(int64_t)row * ldy + q] = acc;
-    }
-}
-
-template <typename V, typename T>
-__device__ inline void batch_tile_l(const BatchDesc &d, int32_t r0, int32_t r1) {
-    rows_runtime<V, T>(d.rp, d.col, (const V *)d.val, d.k, (const T *)d.X, d.ldx, (T *)d.Y, d.ldy,
-                       d.lanes, d.kclass, r0, r1);
-}
-
 // FIXED: the equal-row split of Section 7's parallel CSR on the GPU. A fixed
 // grid of P workgroups; workgroup w owns rows [w M / P, (w + 1) M / P) and
 // nothing rebalances them, so a cluster of heavy rows makes laggards unless
@@ -395,7 +337,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_fixed(int32_t nrows, int32_t pa
                                                        int KM) {
     const int64_t w = blockIdx.x;
     const int32_t r0 = (int32_t)(w * nrows / parts), r1 = (int32_t)((w + 1) * nrows / parts);
-    rows_runtime<V, T>(rp, col, val, k, X, ldx, Y, ldy, L, KM, r0, r1);
+    rows_runtime<V, T, kBlock>(rp, col, val, k, X, ldx, Y, ldy, L, KM, r0, r1, threadIdx.x);
 }
 
 // ---- COO -------------------------------------------------------------------------
@@ -611,57 +553,6 @@ hipError_t semiring_by_type(const SpmvArgs &a, hipStream_t s) {
     }
 }
 
-// Persistent grid with one work queue per XCD (workgroups are dealt to the
-// 8 XCDs round-robin): a workgroup takes tiles from its own XCD's queue, whose
-// matrices' x then stays in that XCD's L2, and when it is empty from the
-// other queues in turn. Every pull either returns a tile or finds a queue
-// exhausted, and each workgroup stops after finding all of them exhausted, so
-// the grid always drains. VT is the value type shared by every item, or -1 for
-// a batch that mixes them (that instance carries every path and so more
-// registers).
-template <int VT>
-__global__ __launch_bounds__(kBlock) void k_spmv_batch(const BatchDesc *__restrict__ descs,
-                                                       const int32_t *__restrict__ qent,
-                                                       BatchQueues qs, int32_t *counters) {
-    __shared__ int32_t tile_s;
-    const int home = blockIdx.x % kBatchQueues;
-    for (int step = 0; step < kBatchQueues;) {
-        const int q = (home + step) % kBatchQueues;
-        if (threadIdx.x == 0) tile_s = atomicAdd(&counters[q], 1);
-        __syncthreads();
-        const int32_t tile = tile_s;
-        __syncthreads();
-        if (tile >= qs.qtiles[q]) {                   // queue exhausted: next one
-            ++step;
-            continue;
-        }
-        int32_t lo = qs.qbegin[q], hi = qs.qbegin[q + 1] - 1;   // last matrix starting <= tile
-        while (lo < hi) {
-            const int32_t mid = (lo + hi + 1) >> 1;
-            if (descs[qent[mid]].tile_begin <= tile) lo = mid;
-            else hi = mid - 1;
-        }
-        const BatchDesc d = descs[qent[lo]];
-        const int32_t r0 = (tile - d.tile_begin) * d.rows_per_tile;
-        const int32_t r1 = min(d.nrows, r0 + d.rows_per_tile);
-        if constexpr (VT == VAL_F64) {
-            batch_tile_l<double, double>(d, r0, r1);
-        } else if constexpr (VT == VAL_F32) {
-            batch_tile_l<float, float>(d, r0, r1);
-        } else if constexpr (VT == VAL_BF16) {
-            batch_tile_l<uint16_t, float>(d, r0, r1);
-        } else {
-            if (d.vtype == VAL_F64) batch_tile_l<double, double>(d, r0, r1);
-            else if (d.vtype == VAL_F32) batch_tile_l<float, float>(d, r0, r1);
-            else batch_tile_l<uint16_t, float>(d, r0, r1);
-        }
-    }
-}
-
-__global__ void k_batch_reset(int32_t *counters) {
-    if (threadIdx.x < kBatchQueues) counters[threadIdx.x] = 0;
-}
-
 // ---- launch helpers ---------------------------------------------------------------------
 
 template <typename V, typename T, int L, int KM>
@@ -785,36 +676,6 @@ hipError_t launch_spmv(const SpmvArgs &a, int variant, hipStream_t s) {
     case VAL_BF16: return spmv_t<uint16_t, float>(a, variant, s);
     default: return hipErrorInvalidValue;
     }
-}
-
-hipError_t launch_batch_reset(int32_t *counters, hipStream_t s) {
-    hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(kWave), 0, s, counters);
-    return hipGetLastError();
-}
-
-int32_t batch_grid_size() { return 256 * 8; }   // 8 resident workgroups per CU
-
-hipError_t launch_spmv_batch(const BatchDesc *descs, const int32_t *qent, const BatchQueues &qs,
-                             int32_t *counters, int32_t grid, int vtype, hipStream_t s) {
-    if (qs.qbegin[kBatchQueues] <= 0) return hipSuccess;
-    switch (vtype) {
-    case VAL_F64:
-        hipLaunchKernelGGL(k_spmv_batch<VAL_F64>, dim3(grid), dim3(kBlock), 0, s, descs, qent, qs,
-                           counters);
-        break;
-    case VAL_F32:
-        hipLaunchKernelGGL(k_spmv_batch<VAL_F32>, dim3(grid), dim3(kBlock), 0, s, descs, qent, qs,
-                           counters);
-        break;
-    case VAL_BF16:
-        hipLaunchKernelGGL(k_spmv_batch<VAL_BF16>, dim3(grid), dim3(kBlock), 0, s, descs, qent, qs,
-                           counters);
-        break;
-    default:
-        hipLaunchKernelGGL(k_spmv_batch<-1>, dim3(grid), dim3(kBlock), 0, s, descs, qent, qs,
-                           counters);
-    }
-    return hipGetLastError();
 }
 
 }  // namespace mxe

@@ -83,6 +83,9 @@ struct Plan {
     std::vector<int32_t> qent;          // per-XCD queue entries (desc indices)
     BatchQueues queues{};
     int32_t *counters = nullptr;        // device: kBatchQueues counters, then qent
+    size_t lds = 0;                     // dynamic LDS of the launch
+    int vtype = -1;                     // ValType shared by the items, or -1
+    int32_t grid = 0;                   // resident workgroups of the batch kernel
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     hipStream_t capture_stream = nullptr;

@@ -1,0 +1,130 @@
+// The column-slab product of one workgroup block, shared by the slab SpMV
+// kernel (one block per workgroup) and the persistent batch kernel (blocks of
+// many matrices pulled from per-XCD queues). Layout and geometry: SlabGeom in
+// internal.h, built by kernels_slab.hip.
+#pragma once
+
+#include "device_common.h"
+#include "internal.h"
+
+namespace mxe {
+
+constexpr int kSlabBlock = 1024;                    // 16 wavefronts
+constexpr int kSubBlocks = kSlabBlock / kWave;      // wavefront sub-blocks per block
+constexpr int kSlabMax = 64;                        // column slabs per layout
+// 64-entry chunks each wavefront keeps in flight (fewer for wide right-hand sides)
+template <int KM> struct SlabUnroll { static constexpr int value = KM <= 2 ? 4 : KM <= 4 ? 2 : 1; };
+
+template <typename V, typename T> struct SlabVal;
+template <> struct SlabVal<double, double> {
+    __device__ static double get(double v) { return v; }
+};
+template <> struct SlabVal<float, float> {
+    __device__ static float get(float v) { return v; }
+};
+template <> struct SlabVal<uint16_t, float> {
+    __device__ static float get(uint16_t v) { return bf16_to_f32(v); }
+};
+
+// Block `block` of the layout, by a workgroup of kSlabBlock threads on XCD
+// `xcd`; tid is the thread's index in it. yp: LDS for the block's partial y (rows_per_block x KM values of T);
+// soff: LDS for the wavefronts' group offsets. The workgroup walks the slabs
+// in its rotation together (a barrier after each slab), starting at a slab
+// tied to its XCD, so all its wavefronts gather from the same L2-resident x
+// slice; inside a slab a wavefront loads up to SlabUnroll chunks of its group
+// at once, issues their x gathers together, then reduces each chunk by row.
+// The first batch of the next slab's group is loaded before each barrier.
+// The caller separates two calls on one workgroup by a barrier.
+template <typename V, typename T, int KM, int SR>
+__device__ __attribute__((always_inline)) inline void
+slab_block(const SlabGeom &g, int32_t block, int xcd, const int32_t *__restrict__ off,
+           const uint32_t *__restrict__ idx, const V *__restrict__ val, int32_t k,
+           const T *__restrict__ X, int64_t ldx, T *__restrict__ Y, int64_t ldy, int vec_x,
+           T *yp, int32_t (*soff)[kSlabMax + 1], int tid) {
+    using S = Semiring<SR, T>;
+    const int wave = tid / kWave, lane = tid % kWave;
+    const int32_t R = g.rows_per_block;
+    for (int i = tid; i < R * KM; i += kSlabBlock) yp[i] = S::identity();
+    T *ywave = yp + (int64_t)wave * g.rows_per_sub * KM;
+    // this wavefront's groups (one per slab) and their offsets
+    const int32_t *o = off + ((int64_t)block * kSubBlocks + wave) * g.slabs;
+    for (int s = lane; s <= g.slabs; s += kWave) soff[wave][s] = o[s];
+    __syncthreads();
+    const int s0 = (int)(((int64_t)xcd * g.slabs) / 8);
+    const uint32_t cmask = (1u << g.cbits) - 1u;
+    constexpr int kD = SlabUnroll<KM>::value;
+    uint32_t u[kD];
+    T a[kD];
+    auto load_batch = [&](int32_t c, int32_t e) {             // up to kD chunks of [c, e)
+#pragma unroll
+        for (int j = 0; j < kD; ++j) {
+            const int32_t p = c + j * kWave + lane;
+            const bool v = p < e;
+            u[j] = v ? idx[p] : 0xffffffffu;
+            a[j] = v ? SlabVal<V, T>::get(val[p]) : T(0);
+        }
+    };
+    load_batch(soff[wave][s0], soff[wave][s0 + 1]);
+    for (int t = 0; t < g.slabs; ++t) {                       // same count in every wavefront
+        const int s = s0 + t < g.slabs ? s0 + t : s0 + t - g.slabs;
+        const int32_t b = soff[wave][s], e = soff[wave][s + 1];
+        for (int32_t c = b; c < e; c += kD * kWave) {
+            if (c != b) load_batch(c, e);                     // the first batch is already loaded
+            T xv[kD][KM];
+#pragma unroll
+            for (int j = 0; j < kD; ++j) {
+                const bool v = u[j] != 0xffffffffu;
+                const T *xr = X + (int64_t)(v ? (u[j] & cmask) : 0) * ldx;
+                if constexpr (KM > 1) {
+                    if (vec_x) {                              // k == KM, 16-byte aligned rows
+                        constexpr int W = (16 / (int)sizeof(T)) < KM ? 16 / (int)sizeof(T) : KM;
+                        typedef T vec_t __attribute__((ext_vector_type(W)));
+#pragma unroll
+                        for (int q = 0; q < KM; q += W) {
+                            const vec_t w = *reinterpret_cast<const vec_t *>(xr + q);
+#pragma unroll
+                            for (int r = 0; r < W; ++r) xv[j][q + r] = v ? w[r] : T(0);
+                        }
+                        continue;
+                    }
+                }
+#pragma unroll
+                for (int q = 0; q < KM; ++q) xv[j][q] = (v && (KM == 1 || q < k)) ? xr[q] : T(0);
+            }
+#pragma unroll
+            for (int j = 0; j < kD; ++j) {
+                if (c + j * kWave >= e) break;                // uniform per wavefront
+                // padding lanes (key 0xffffffff) sit after every valid lane
+                const uint32_t key = u[j] != 0xffffffffu ? (u[j] >> g.cbits) : 0xffffffffu;
+                T prod[KM];
+#pragma unroll
+                for (int q = 0; q < KM; ++q) prod[q] = S::mul(a[j], xv[j][q]);
+                if constexpr (SR == 0) segmented_scan<T, KM>(key, prod);
+                else segmented_scan_op<S, T, KM>(key, prod);
+                const uint32_t nxt = __shfl_down(key, 1);
+                const bool tail = key != 0xffffffffu && (lane == kWave - 1 || nxt != key);
+                if (tail) {
+#pragma unroll
+                    for (int q = 0; q < KM; ++q)
+                        ywave[(int64_t)key * KM + q] = S::add(ywave[(int64_t)key * KM + q], prod[q]);
+                }
+                // the next chunk's tails may update the same rows: keep order
+                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+            }
+        }
+        if (t + 1 < g.slabs) {                                // next slab's first batch, issued
+            const int sn = s + 1 < g.slabs ? s + 1 : 0;       // before the barrier waits
+            load_batch(soff[wave][sn], soff[wave][sn + 1]);
+        }
+        __syncthreads();
+    }
+    const int64_t row0 = (int64_t)block * R;
+    for (int i = tid; i < R * KM; i += kSlabBlock) {
+        const int64_t row = row0 + i / KM;
+        const int q = i % KM;
+        if (row < g.nrows && (KM == 1 || q < k)) Y[row * ldy + q] = yp[i];
+    }
+}
+
+}  // namespace mxe

@@ -113,6 +113,63 @@ def test_batch_plan_graph_replays(ctx):
     ctx.batch_destroy(plan)
 
 
+def _slab_units(A, k, storage):
+    """Slab size (in 64 KiB units) that cuts x into about 8 slabs."""
+    xb = 8 if storage == "f64" else 4
+    kc = 1 << (k - 1).bit_length()
+    return max(1, -(-(A.ncols * xb * kc) // (8 * 65536)))
+
+
+def test_batch_slab_units(ctx):
+    """Items whose variant is the column-slab kernel run as the blocks of its
+    layout inside the persistent launch, next to row-tile items: k equal to its
+    class (whole-row vector loads) and below it, a padded X (ldx > k, no vector
+    loads), FP64 / FP32 / BF16 storage. Checked against the oracle directly and
+    after graph replays, which agree bit for bit with each other."""
+    mats = _pool(7, 500, rows=(30_000, 90_000))
+    storages = ["f32", "f32", "f64", "bf16", "f32", "f64", "f32"]
+    ks = [1, 4, 3, 16, 8, 2, 4]
+    slab = [True, True, True, True, False, True, True]
+    padded = [False, False, False, False, False, False, True]
+    handles = [ctx.permute(ctx.register(A, st), 13) for A, st in zip(mats, storages)]
+    B0 = []
+    for H, A, k, st, sl in zip(handles, mats, ks, storages, slab):
+        rperm, cperm = ctx.get_permutation(H)
+        B0.append(synth.CSR(A.nrows, A.ncols, *oracle.permute_csr(A, rperm, cperm)))
+        var = mx.variant(mx.VAR_SLAB, _slab_units(A, k, st)) if sl else mx.variant(mx.VAR_GROUP, 8)
+        ctx.set_variant(H, k, var)
+    Xs = [_rand_x(A, k, 70 + i) for i, (A, k) in enumerate(zip(mats, ks))]
+    dts = [torch.float64 if st == "f64" else torch.float32 for st in storages]
+    Xt = []
+    for X, dt, pad, k in zip(Xs, dts, padded, ks):
+        if pad:                                   # ldx = k + 1: rows off the 16-byte grid
+            buf = torch.zeros((X.shape[0], k + 1), dtype=dt, device="cuda")
+            buf[:, :k] = torch_vec(X, dt)
+            Xt.append(buf[:, :k])
+        else:
+            Xt.append(torch_vec(X, dt))
+    Ys = [torch.full((A.nrows, k) if k > 1 else (A.nrows,), float("nan"), dtype=dt, device="cuda")
+          for A, k, dt in zip(mats, ks, dts)]
+    print("slab batch", [(A.nrows, k, st) for A, k, st in zip(mats, ks, storages)], flush=True)
+    ctx.spmv_batch(list(zip(handles, Xt, Ys)))
+    torch.cuda.synchronize()
+    for i, (Bo, X, Y, st) in enumerate(zip(B0, Xs, Ys, storages)):
+        assert spmv_error(Bo, X, Y.cpu().numpy().astype(np.float64), st) <= TOL[st], (i, st)
+    first = [Y.clone() for Y in Ys]
+    plan = ctx.batch_create(list(zip(handles, Xt, Ys)))
+    for replay in range(3):
+        for Y in Ys:
+            Y.fill_(float("nan"))
+        ctx.batch_launch(plan)
+        torch.cuda.synchronize()
+        _ = torch.ones(1000, device="cuda").sum().item()        # eager work between replays
+        for i, (Y, Y1) in enumerate(zip(Ys, first)):
+            assert torch.equal(Y, Y1), (replay, i)
+    ctx.batch_destroy(plan)
+    for H in handles:
+        ctx.release(H)
+
+
 def test_batch_mixed_storage(ctx):
     """FP64, FP32 and BF16 items in one persistent launch (the instance that
     carries every value type), directly and from a graph replay."""
