@@ -213,17 +213,19 @@ static TuneKey tune_key(const Matrix &A, int32_t k) {
 // slab size: `units` x 64 KiB of x
 static int64_t slab_bytes_of(int units) { return (int64_t)units << 16; }
 
-static mxe_status ensure_slab(mxe_ctx *ctx, Matrix &A, int kclass, int units, hipStream_t s,
-                              const Matrix::Slab **out) {
-    const auto key = std::make_pair(kclass, units);
+// cus: the compute units whose workgroups share the matrix, which sizes the
+// row blocks (all of the device for a single product, one XCD's in a batch)
+static mxe_status ensure_slab(mxe_ctx *ctx, Matrix &A, int kclass, int units, int cus,
+                              hipStream_t s, const Matrix::Slab **out) {
+    const auto key = std::make_tuple(kclass, units, cus);
     auto it = A.slabs.find(key);
     if (it != A.slabs.end()) {
         *out = &it->second;
         return MXE_OK;
     }
     Matrix::Slab sl;
-    if (!slab_geometry(A.nrows, A.ncols, kclass, vtype_of(A.storage), ctx->cu_count,
-                       slab_bytes_of(units), &sl.g))
+    if (!slab_geometry(A.nrows, A.ncols, kclass, vtype_of(A.storage), cus, slab_bytes_of(units),
+                       &sl.g))
         return fail(MXE_ERR_UNSUPPORTED, "column-slab layout does not fit this matrix");
     const int vb = val_bytes_of(A.storage);
     const size_t noff = slab_offsets_count(sl.g);
@@ -267,7 +269,8 @@ static mxe_status prepare_args(mxe_ctx *ctx, Matrix &A, int variant, int32_t k, 
     *a = make_args(A, k, X, ldx, Y, ldy);
     if (family == MXE_VAR_SLAB) {
         const Matrix::Slab *sl;
-        if ((st = ensure_slab(ctx, A, kclass_of(k), variant & 0xff, s, &sl))) return st;
+        if ((st = ensure_slab(ctx, A, kclass_of(k), variant & 0xff, ctx->cu_count, s, &sl)))
+            return st;
         a->slab = &sl->g;
         a->slab_off = sl->off;
         a->slab_idx = sl->idx;
@@ -300,7 +303,7 @@ static mxe_status tune(mxe_ctx *ctx, Matrix &A, int32_t k, hipStream_t s, TuneRe
                           slab_bytes_of(units), &g))
             cands.push_back(MXE_VARIANT(MXE_VAR_SLAB, units));
     }
-    std::set<std::pair<int, int>> had;                // layouts other work may be using
+    std::set<std::tuple<int, int, int>> had;          // layouts other work may be using
     for (const auto &kv : A.slabs) had.insert(kv.first);
     hipEvent_t e0, e1;
     MXE_HIP(hipEventCreate(&e0));
@@ -350,8 +353,8 @@ static mxe_status tune(mxe_ctx *ctx, Matrix &A, int32_t k, hipStream_t s, TuneRe
     // column-slab layouts built here for this k class and not chosen are freed
     // (stream-ordered after the timing launches)
     for (auto it = A.slabs.begin(); it != A.slabs.end();) {
-        if (it->first.first == kc && !had.count(it->first) &&
-            (result != MXE_OK || MXE_VARIANT(MXE_VAR_SLAB, it->first.second) != r.variant)) {
+        if (std::get<0>(it->first) == kc && !had.count(it->first) &&
+            (result != MXE_OK || MXE_VARIANT(MXE_VAR_SLAB, std::get<1>(it->first)) != r.variant)) {
             drop_slab(ctx, A, it->second, s);
             it = A.slabs.erase(it);
         } else {
@@ -1092,8 +1095,14 @@ static mxe_status build_descs(mxe_ctx *ctx, int32_t count, const mxe_item *items
         d.lanes = std::max(r.group_lanes, d.kclass);   // set_variant may force fewer
         d.rows_per_tile = (kBatchBlock / d.lanes) * 2;
         if ((r.variant & 0xf00) == MXE_VAR_SLAB) {
+            // the item's x is gathered by one XCD's workgroups: a layout with
+            // row blocks sized for them (fewer, larger blocks, so fewer slab
+            // phases per row), else the tuned layout
             const Matrix::Slab *sl;
-            if ((st = ensure_slab(ctx, *A, d.kclass, r.variant & 0xff, s, &sl))) return st;
+            const int xcd_cus = std::max(1, ctx->cu_count / kBatchQueues);
+            if (ensure_slab(ctx, *A, d.kclass, r.variant & 0xff, xcd_cus, s, &sl) != MXE_OK &&
+                (st = ensure_slab(ctx, *A, d.kclass, r.variant & 0xff, ctx->cu_count, s, &sl)))
+                return st;
             const int eb = elem_bytes_of(A->storage);
             d.slab = sl->g;
             d.slab_off = sl->off;

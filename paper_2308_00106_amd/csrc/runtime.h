@@ -12,6 +12,7 @@
 #include <mutex>
 #include <string>
 #include <thread>
+#include <tuple>
 #include <vector>
 
 #include "../../include/mxe.h"
@@ -57,7 +58,8 @@ struct Matrix {
         uint32_t *idx = nullptr;
         void *val = nullptr;
     };
-    std::map<std::pair<int, int>, Slab> slabs;   // (k class, slab size in 64 KiB) -> layout
+    // (k class, slab size in 64 KiB, CUs the geometry is sized for) -> layout
+    std::map<std::tuple<int, int, int>, Slab> slabs;
     std::atomic<int> busy{0};           // serving requests queued or running
     std::vector<void *> allocs;         // device allocations to free
 };

@@ -191,7 +191,7 @@ def _force(ctx, H, k, v):
 
 
 @pytest.mark.parametrize("name,make", CSR_CASES)
-@pytest.mark.parametrize("k", [1, 2, 3, 16, 17])
+@pytest.mark.parametrize("k", [1, 2, 3, 4, 8, 16, 17])
 def test_spmv_all_variants_f64(ctx, name, make, k):
     A0 = make()
     X = synth.vector(A0.ncols, 2, k=k)
@@ -218,7 +218,7 @@ def test_spmv_all_variants_f64(ctx, name, make, k):
 @pytest.mark.parametrize("name,make", CSR_CASES[:4] + CSR_CASES[5:])
 def test_spmv_reduced_precision(ctx, storage, name, make):
     A0 = make()
-    for k in (1, 4, 8):
+    for k in (1, 4, 8, 12, 16):
         X = synth.vector(A0.ncols, 2, k=k)
         A = ctx.register(A0, storage)
         Xt = torch_vec(X, torch.float32)
@@ -261,7 +261,7 @@ def test_identity_original_space(ctx):
     ctx.release(A)
 
 
-@pytest.mark.parametrize("k", [1, 5])
+@pytest.mark.parametrize("k", [1, 5, 16])
 def test_every_variant_is_bitwise_repeatable(ctx, k):
     """Each variant sums every row in a fixed order: two runs give the same bits."""
     A0 = synth.config3(1, n=60_000)
