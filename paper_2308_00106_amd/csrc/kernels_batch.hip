@@ -63,7 +63,8 @@ template <int VT>
 __global__ __launch_bounds__(kBatchBlock) void k_spmv_batch(const BatchDesc *__restrict__ descs,
                                                            const int32_t *__restrict__ qent,
                                                            BatchQueues qs, int32_t *counters) {
-    extern __shared__ unsigned char smem[];                  // slab units: the block's partial y
+    // slab units: the block's partial y (16-byte aligned for FP64 and vector LDS access)
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     __shared__ int32_t soff[kSubBlocks][kSlabMax + 1];
     __shared__ int32_t unit_s;
     const int home = blockIdx.x % kBatchQueues;

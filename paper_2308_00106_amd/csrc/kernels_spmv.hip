@@ -305,9 +305,6 @@ __global__ __launch_bounds__(kBlock) void k_merge_fixup(int32_t ntiles, const Ca
     const int32_t row = carry[w].row;
     if (row < 0) return;
     if (w > 0 && carry[w - 1].row == row) return;        // not the first carry of this row
-    double s[KM];
-#pragma unroll
-    for (int q = 0; q < KM; ++q) s[q] = 0.0;
     // carries are partial sums in T; add them in T in slice order
     T t[KM];
 #pragma unroll
@@ -319,7 +316,6 @@ __global__ __launch_bounds__(kBlock) void k_merge_fixup(int32_t ntiles, const Ca
 #pragma unroll
     for (int q = 0; q < KM; ++q)
         if (KM == 1 || q < k) y[q] = t[q] + y[q];
-    (void)s;
 }
 
 // FIXED: the equal-row split of Section 7's parallel CSR on the GPU. A fixed
