@@ -170,6 +170,46 @@ def test_batch_slab_units(ctx):
         ctx.release(H)
 
 
+def test_batch_slab_layout_within_budget():
+    """A batch gives a slab-tuned item a second layout with row blocks sized
+    for one XCD; when the HBM budget has no room for it the item runs on its
+    tuned layout, with a correct result either way."""
+    A0 = synth.config2(1, n=200_000)
+    k = 4
+    X = synth.vector(A0.ncols, 6, k=k)
+
+    def setup(c):
+        A = c.register(A0, "f32")
+        H = c.permute(A, 5)
+        c.set_variant(H, k, mx.variant(mx.VAR_SLAB, 4))
+        Xd = torch_vec(X, torch.float32)
+        Y = torch.empty((A0.nrows, k), dtype=torch.float32, device="cuda")
+        c.spmv(H, Xd, Y)                                  # builds the tuned layout
+        torch.cuda.synchronize()
+        rperm, cperm = c.get_permutation(H)
+        Bo = synth.CSR(A0.nrows, A0.ncols, *oracle.permute_csr(A0, rperm, cperm))
+        return A, H, Xd, Bo
+
+    def run_batch(c, H, Xd, Bo):
+        Y = torch.full((A0.nrows, k), float("nan"), dtype=torch.float32, device="cuda")
+        c.spmv_batch([(H, Xd, Y)])
+        torch.cuda.synchronize()
+        assert spmv_error(Bo, X, Y.cpu().numpy().astype(np.float64), "f32") <= TOL["f32"]
+
+    with mx.Context(0) as c1:
+        A, H, Xd, Bo = setup(c1)
+        resident = c1.matrix_info(A).device_bytes + c1.matrix_info(H).device_bytes
+        before = c1.matrix_info(H).device_bytes
+        run_batch(c1, H, Xd, Bo)
+        grown = c1.matrix_info(H).device_bytes - before
+        assert grown >= A0.nnz * 8                        # the per-XCD layout was built
+    with mx.Context(0, budget_bytes=resident + grown // 2) as c2:
+        A, H, Xd, Bo = setup(c2)
+        before = c2.matrix_info(H).device_bytes
+        run_batch(c2, H, Xd, Bo)
+        assert c2.matrix_info(H).device_bytes == before   # no room: the tuned layout ran
+
+
 def test_batch_mixed_storage(ctx):
     """FP64, FP32 and BF16 items in one persistent launch (the instance that
     carries every value type), directly and from a graph replay."""
