@@ -327,7 +327,7 @@ def main():
     # the product's x reads are nnz random 8-byte gathers: its gather rate against
     # the device's measured ceiling, for an XCD-local slab (as the slab kernel
     # reads x) and for the whole of x
-    slab_units = var_b & 0xff if (var_b & 0xf00) == 0x300 else 16
+    slab_units = var_b & 0x7f if (var_b & 0xf00) == 0x300 else 16      # size without the 0x80 flag
     g_slab = ctx.probe_gather(8 * (slab_units << 16), A0.nnz, per_xcd=True, stream=stream)
     g_all = ctx.probe_gather(A0.ncols * 8 // 64 * 64, A0.nnz, per_xcd=False, stream=stream)
     gather = {"achieved_gps": round(A0.nnz / (perm_us * 1e-6) / 1e9, 1),

@@ -217,11 +217,14 @@ mxe_status mxe_scatter_y(mxe_ctx *ctx, mxe_mat b, int32_t k, const void *Yp, int
  * MXE_VAR_MERGE (merge-path split of rows + nonzeros, equal work per group), or
  * MXE_VAR_SLAB with lanes = slab size in units of 64 KiB (1..64): a column-slab layout,
  * built once per matrix and right-hand-side class, whose workgroups keep
- * their rows' partial sums in LDS and gather x one L2-sized slab at a time. */
+ * their rows' partial sums in LDS and gather x one L2-sized slab at a time;
+ * row blocks are sized for two workgroups per compute unit, or for one when
+ * MXE_SLAB_ONE_PER_CU is added to the slab size. */
 #define MXE_VAR_GROUP   0x000
 #define MXE_VAR_BINNED  0x100
 #define MXE_VAR_MERGE   0x200
 #define MXE_VAR_SLAB    0x300
+#define MXE_SLAB_ONE_PER_CU 0x80
 /* MXE_VAR_FIXED with lanes per row (1..64): Section 7's equal-row split, a
  * fixed grid of 2048 workgroups each owning an equal contiguous share of rows,
  * nothing rebalanced (the case where the paper sees randomization help). */

@@ -9,5 +9,5 @@ binding; see `mxe.Context`.
 from .mxe import (  # noqa: F401
     BF16, COLS, F32, F64, GRADIENT, ROWS, SPACE_ORIGINAL, SPACE_PERMUTED, VAR_BINNED, VAR_GROUP,
     VAR_COO, VAR_FIXED, VAR_MERGE, VAR_SLAB, Context, MxeError, abi_version, exported_symbols, last_error, load_library,
-    SR_MIN_PLUS, SR_OR_AND, SR_PLUS_TIMES, status_string, validate_csr, variant,
+    SLAB_ONE_PER_CU, SR_MIN_PLUS, SR_OR_AND, SR_PLUS_TIMES, status_string, validate_csr, variant,
 )

@@ -212,6 +212,12 @@ static TuneKey tune_key(const Matrix &A, int32_t k) {
 
 // slab size: `units` x 64 KiB of x
 static int64_t slab_bytes_of(int units) { return (int64_t)units << 16; }
+// a SLAB variant's slab size and the CUs its row blocks are sized for (two
+// workgroups per CU; MXE_SLAB_ONE_PER_CU: one, so blocks for half the CUs)
+static int slab_units_of(int variant) { return variant & (MXE_SLAB_ONE_PER_CU - 1); }
+static int slab_cus_of(const mxe_ctx *ctx, int variant) {
+    return (variant & MXE_SLAB_ONE_PER_CU) ? std::max(1, ctx->cu_count / 2) : ctx->cu_count;
+}
 
 // cus: the compute units whose workgroups share the matrix, which sizes the
 // row blocks (all of the device for a single product, one XCD's in a batch)
@@ -269,7 +275,8 @@ static mxe_status prepare_args(mxe_ctx *ctx, Matrix &A, int variant, int32_t k, 
     *a = make_args(A, k, X, ldx, Y, ldy);
     if (family == MXE_VAR_SLAB) {
         const Matrix::Slab *sl;
-        if ((st = ensure_slab(ctx, A, kclass_of(k), variant & 0xff, ctx->cu_count, s, &sl)))
+        if ((st = ensure_slab(ctx, A, kclass_of(k), slab_units_of(variant), slab_cus_of(ctx, variant),
+                              s, &sl)))
             return st;
         a->slab = &sl->g;
         a->slab_off = sl->off;
@@ -281,9 +288,10 @@ static mxe_status prepare_args(mxe_ctx *ctx, Matrix &A, int variant, int32_t k, 
 
 // ---- autotuner ---------------------------------------------------------------------
 // Times every variant (GROUP with 1..64 lanes, BINNED, FIXED, MERGE when
-// k <= 4, SLAB with 0.75, 1, 2 and 4 MiB slabs when the layout fits) on the matrix itself
-// with scratch vectors and keeps the fastest; also keeps the fastest GROUP
-// lanes for the persistent batch kernel.
+// k <= 4, SLAB with 0.75, 1, 2 and 4 MiB slabs at two workgroups per CU and
+// 1, 1.25 and 1.5 MiB at one, when the layout fits) on the matrix itself
+// with scratch vectors, times the fastest few again and keeps the winner;
+// also keeps the fastest GROUP lanes for the persistent batch kernel.
 static mxe_status tune(mxe_ctx *ctx, Matrix &A, int32_t k, hipStream_t s, TuneResult *out) {
     mxe_status st;
     const int kc = kclass_of(k);
@@ -297,24 +305,46 @@ static mxe_status tune(mxe_ctx *ctx, Matrix &A, int32_t k, hipStream_t s, TuneRe
     cands.push_back(MXE_VARIANT(MXE_VAR_BINNED, 0));
     cands.push_back(MXE_VARIANT(MXE_VAR_FIXED, std::max(kc, 8)));
     if (kc <= 4) cands.push_back(MXE_VARIANT(MXE_VAR_MERGE, 0));
-    for (int units : {12, 16, 32, 64}) {             // 0.75, 1, 2 and 4 MiB of x per slab
+    // 0.75, 1, 2 and 4 MiB of x per slab with two workgroups per CU; 1, 1.25
+    // and 1.5 MiB with one (each workgroup then walks twice the rows per slab)
+    for (int units : {12, 16, 32, 64, 16 | MXE_SLAB_ONE_PER_CU, 20 | MXE_SLAB_ONE_PER_CU,
+                      24 | MXE_SLAB_ONE_PER_CU}) {
+        const int v = MXE_VARIANT(MXE_VAR_SLAB, units);
         SlabGeom g;
-        if (slab_geometry(A.nrows, A.ncols, kc, vtype_of(A.storage), ctx->cu_count,
-                          slab_bytes_of(units), &g))
-            cands.push_back(MXE_VARIANT(MXE_VAR_SLAB, units));
+        if (slab_geometry(A.nrows, A.ncols, kc, vtype_of(A.storage), slab_cus_of(ctx, v),
+                          slab_bytes_of(slab_units_of(v)), &g))
+            cands.push_back(v);
     }
     std::set<std::tuple<int, int, int>> had;          // layouts other work may be using
     for (const auto &kv : A.slabs) had.insert(kv.first);
     hipEvent_t e0, e1;
     MXE_HIP(hipEventCreate(&e0));
     MXE_HIP(hipEventCreate(&e1));
+    // milliseconds per product of variant v over reps launches after a warm-up
+    auto time_variant = [&](int v, int reps, float *per) -> mxe_status {
+        SpmvArgs a;
+        mxe_status st2 = prepare_args(ctx, A, v, kc, xs.p, kc, ys.p, kc, s, &a);
+        if (st2) return st2;
+        hipError_t e = launch_spmv(a, v, s);
+        if (e == hipSuccess) e = hipEventRecord(e0, s);
+        for (int i = 0; i < reps && e == hipSuccess; ++i) e = launch_spmv(a, v, s);
+        if (e == hipSuccess) e = hipEventRecord(e1, s);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e != hipSuccess) return hip_fail(e, "autotune");
+        *per = ms / reps;
+        return MXE_OK;
+    };
+    // stage 1: every candidate, briefly
     const int reps = A.nnz > 4000000 ? 3 : 10;
-    float best = std::numeric_limits<float>::max(), best_group = best;
+    std::vector<std::pair<float, int>> timed;            // (ms per product, variant)
+    float best_group = std::numeric_limits<float>::max();
     TuneResult r{cands[0], 1};
     mxe_status result = MXE_OK;
     for (int v : cands) {
-        SpmvArgs a;
-        if ((result = prepare_args(ctx, A, v, kc, xs.p, kc, ys.p, kc, s, &a))) {
+        float ms = 0;
+        if ((result = time_variant(v, reps, &ms))) {
             // a layout that does not fit the matrix or the HBM budget is not a candidate
             if (result == MXE_ERR_UNSUPPORTED || result == MXE_ERR_BUDGET) {
                 result = MXE_OK;
@@ -322,30 +352,37 @@ static mxe_status tune(mxe_ctx *ctx, Matrix &A, int32_t k, hipStream_t s, TuneRe
             }
             break;
         }
-        hipError_t e = launch_spmv(a, v, s);                  // warm-up
-        for (int i = 0; i < reps && e == hipSuccess; ++i) {
-            if (i == 0) e = hipEventRecord(e0, s);
-            if (e == hipSuccess) e = launch_spmv(a, v, s);
-        }
-        if (e == hipSuccess) e = hipEventRecord(e1, s);
-        if (e == hipSuccess) e = hipEventSynchronize(e1);
-        float ms = 0;
-        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-        if (e != hipSuccess) {
-            result = hip_fail(e, "autotune");
-            break;
-        }
         if (getenv("MXE_LOG"))
             fprintf(stderr, "[mxe] tune rows=%d nnz=%lld k=%d variant 0x%x: %.2f us\n", A.nrows,
-                    (long long)A.nnz, kc, v, 1e3f * ms / reps);
-        if (ms < best) {
-            best = ms;
-            r.variant = v;
-        }
+                    (long long)A.nnz, kc, v, 1e3f * ms);
+        timed.push_back({ms, v});
         // the persistent batch kernel runs multi-RHS items with lanes >= k class
         if ((v & 0xf00) == MXE_VAR_GROUP && (v & 0xff) >= kc && ms < best_group) {
             best_group = ms;
             r.group_lanes = v & 0xff;
+        }
+    }
+    // stage 2: the candidates within 8% of the fastest (two to five of them)
+    // again, interleaved over two rounds of 10 products each, so candidates a
+    // few percent apart are told apart
+    if (result == MXE_OK && !timed.empty()) {
+        std::stable_sort(timed.begin(), timed.end());
+        size_t top = 1;
+        while (top < timed.size() && top < 5 &&
+               (top < 2 || timed[top].first <= 1.08f * timed[0].first))
+            ++top;
+        std::vector<float> total(top, 0.0f);
+        for (int round = 0; round < 2 && result == MXE_OK; ++round)
+            for (size_t i = 0; i < top && result == MXE_OK; ++i) {
+                float ms = 0;
+                if ((result = time_variant(timed[i].second, 10, &ms)) == MXE_OK) total[i] += ms;
+            }
+        if (result == MXE_OK) {
+            const size_t b = std::min_element(total.begin(), total.end()) - total.begin();
+            r.variant = timed[b].second;
+            if (getenv("MXE_LOG"))
+                fprintf(stderr, "[mxe] tune rows=%d k=%d chose 0x%x: %.2f us\n", A.nrows, kc,
+                        r.variant, 1e3f * total[b] / 2);
         }
     }
     (void)hipEventDestroy(e0);
@@ -353,8 +390,10 @@ static mxe_status tune(mxe_ctx *ctx, Matrix &A, int32_t k, hipStream_t s, TuneRe
     // column-slab layouts built here for this k class and not chosen are freed
     // (stream-ordered after the timing launches)
     for (auto it = A.slabs.begin(); it != A.slabs.end();) {
-        if (std::get<0>(it->first) == kc && !had.count(it->first) &&
-            (result != MXE_OK || MXE_VARIANT(MXE_VAR_SLAB, std::get<1>(it->first)) != r.variant)) {
+        const bool chosen = result == MXE_OK && (r.variant & 0xf00) == MXE_VAR_SLAB &&
+                            std::get<1>(it->first) == slab_units_of(r.variant) &&
+                            std::get<2>(it->first) == slab_cus_of(ctx, r.variant);
+        if (std::get<0>(it->first) == kc && !had.count(it->first) && !chosen) {
             drop_slab(ctx, A, it->second, s);
             it = A.slabs.erase(it);
         } else {
@@ -1004,9 +1043,11 @@ mxe_status mxe_set_variant(mxe_ctx *ctx, mxe_mat m, int32_t k, int32_t variant) 
         return fail(MXE_ERR_INVALID_ARG, "unknown variant family");
     if (family == MXE_VAR_SLAB) {
         SlabGeom sg;
-        if (lanes < 1 || lanes > 64) return fail(MXE_ERR_INVALID_ARG, "slab size must be 1..64 x 64 KiB");
-        if (!slab_geometry(A->nrows, A->ncols, kclass_of(k), vtype_of(A->storage), ctx->cu_count,
-                           slab_bytes_of(lanes), &sg))
+        const int units = slab_units_of(variant);
+        if (units < 1 || units > 64)
+            return fail(MXE_ERR_INVALID_ARG, "slab size must be 1..64 x 64 KiB");
+        if (!slab_geometry(A->nrows, A->ncols, kclass_of(k), vtype_of(A->storage),
+                           slab_cus_of(ctx, variant), slab_bytes_of(units), &sg))
             return fail(MXE_ERR_UNSUPPORTED, "column-slab layout does not fit this matrix");
     }
     if (family == MXE_VAR_MERGE && kclass_of(k) > 4)
@@ -1100,8 +1141,9 @@ static mxe_status build_descs(mxe_ctx *ctx, int32_t count, const mxe_item *items
             // phases per row), else the tuned layout
             const Matrix::Slab *sl;
             const int xcd_cus = std::max(1, ctx->cu_count / kBatchQueues);
-            if (ensure_slab(ctx, *A, d.kclass, r.variant & 0xff, xcd_cus, s, &sl) != MXE_OK &&
-                (st = ensure_slab(ctx, *A, d.kclass, r.variant & 0xff, ctx->cu_count, s, &sl)))
+            const int units = slab_units_of(r.variant);
+            if (ensure_slab(ctx, *A, d.kclass, units, xcd_cus, s, &sl) != MXE_OK &&
+                (st = ensure_slab(ctx, *A, d.kclass, units, slab_cus_of(ctx, r.variant), s, &sl)))
                 return st;
             const int eb = elem_bytes_of(A->storage);
             d.slab = sl->g;

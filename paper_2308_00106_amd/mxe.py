@@ -27,6 +27,7 @@ INPUT_DEVICE = OUTPUT_DEVICE = 0x1
 ROWS, COLS, GRADIENT = 0x1, 0x2, 0x4
 SPACE_PERMUTED, SPACE_ORIGINAL = 0x0, 0x1
 VAR_GROUP, VAR_BINNED, VAR_MERGE, VAR_SLAB, VAR_FIXED, VAR_COO = 0x000, 0x100, 0x200, 0x300, 0x400, 0x500
+SLAB_ONE_PER_CU = 0x80            # SLAB lanes flag: row blocks for one workgroup per CU
 SR_PLUS_TIMES, SR_MIN_PLUS, SR_OR_AND = 0, 1, 2
 
 

@@ -173,6 +173,7 @@ def test_entropy_rejects_bad_grid(ctx):
 VARIANTS = [mx.variant(mx.VAR_GROUP, lanes) for lanes in (1, 2, 4, 8, 16, 32, 64)] + \
            [mx.variant(mx.VAR_BINNED), mx.variant(mx.VAR_MERGE),
             mx.variant(mx.VAR_SLAB, 1), mx.variant(mx.VAR_SLAB, 32),   # 64 KiB and 2 MiB slabs
+            mx.variant(mx.VAR_SLAB, 16 | mx.SLAB_ONE_PER_CU),          # row blocks for one per CU
             mx.variant(mx.VAR_FIXED, 4), mx.variant(mx.VAR_FIXED, 16), mx.variant(mx.VAR_COO)]
 
 
