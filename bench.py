@@ -58,16 +58,18 @@ def kernel_source_hash(variant_hex: str = "0x300") -> str:
 
 
 def measured_traffic(variant_hex: str):
-    """HBM traffic per launch from the committed rocprofv3 PMC summary, if it
-    was taken on the current SpMV kernel source and variant; else None."""
+    """HBM traffic per launch from the committed rocprofv3 PMC summary (one
+    JSON line per profiled variant), if it was taken on the current SpMV
+    kernel source and this variant; else None."""
     try:
         with open(TRAFFIC_FILE) as f:
-            t = json.load(f)
+            entries = [json.loads(line) for line in f if line.strip()]
     except (OSError, ValueError):
         return None
-    if t.get("variant") != variant_hex or t.get("kernel_source_hash") != kernel_source_hash(variant_hex):
-        return None
-    return t.get("bytes_per_launch")
+    for t in entries:
+        if t.get("variant") == variant_hex and t.get("kernel_source_hash") == kernel_source_hash(variant_hex):
+            return t.get("bytes_per_launch")
+    return None
 
 
 def cpu_baseline(A, x, rperm_seed, reps, grid, budget_s=12.0):
