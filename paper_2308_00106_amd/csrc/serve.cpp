@@ -6,12 +6,14 @@
 // free and the HBM budget covers the resident matrices plus the vectors of
 // every request in flight, merges queued requests on the same matrix into one
 // multi-right-hand-side product (packed into a staging matrix, so the sparse
-// matrix streams once for all of them), issues the work round-robin on
-// several device streams so launches overlap, and retires requests when their
+// matrix streams once for all of them), issues each launch on whichever of
+// several device streams has the least work queued, so launches overlap and
+// small requests do not wait behind large ones, and retires requests when their
 // completion event fires. Requests arriving while others run are admitted as
 // soon as slots and budget free up.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 
 #include "runtime.h"
@@ -37,6 +39,8 @@ struct Launch {
     std::vector<std::shared_ptr<Request>> reqs;
     hipEvent_t ev = nullptr;
     uint64_t bytes = 0;
+    uint64_t work = 0;                  // bytes the product moves (matrix and vectors)
+    int stream = 0;                     // index into Server::streams
 };
 
 }  // namespace
@@ -45,7 +49,7 @@ struct Server {
     mxe_ctx *ctx = nullptr;
     mxe_serve_config cfg{};
     std::vector<hipStream_t> streams;
-    int next_stream = 0;
+    std::vector<uint64_t> stream_work;   // bytes of the products queued on each stream
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
     std::deque<std::shared_ptr<Request>> queue;
@@ -88,6 +92,7 @@ void Server::retire_done() {
             --inflight_reqs;
         }
         inflight_bytes -= l.bytes;
+        stream_work[l.stream] -= l.work;
         free_events.push_back(l.ev);
         inflight[i] = std::move(inflight.back());
         inflight.pop_back();
@@ -176,8 +181,11 @@ bool Server::admit_one(std::unique_lock<std::mutex> &lk) {
                 queue.erase(it);
                 break;
             }
-    hipStream_t s = streams[next_stream];
-    next_stream = (next_stream + 1) % (int)streams.size();
+    // the stream with the least work queued, so a small request does not
+    // wait behind a large one while another stream is idle
+    const int si = (int)(std::min_element(stream_work.begin(), stream_work.end()) - stream_work.begin());
+    const uint64_t work = request_bytes(*head->mat, K);
+    hipStream_t s = streams[si];
     // reserve the slots and bytes, then issue without holding the queue lock
     // so submitters are not blocked by the device calls
     for (auto &r : group) r->state = 1;
@@ -203,6 +211,9 @@ bool Server::admit_one(std::unique_lock<std::mutex> &lk) {
         l.reqs = group;
         l.ev = ev;
         l.bytes = bytes;
+        l.work = work;
+        l.stream = si;
+        stream_work[si] += work;
         inflight.push_back(std::move(l));
     } else {
         inflight_reqs -= (int)group.size();
@@ -251,6 +262,7 @@ mxe_status serve_start(mxe_ctx *ctx, const mxe_serve_config *cfg) {
         MXE_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));   // default priority
         srv->streams.push_back(s);
     }
+    srv->stream_work.assign(srv->streams.size(), 0);
     Server *raw = srv.release();
     ctx->server = raw;
     raw->th = std::thread([raw] { raw->run(); });
