@@ -179,6 +179,7 @@ template <typename T> struct Semiring<2, T> {
 // 1 and 3 and row_bcast:31 into rows 2 and 3. A lane adds the moved value only
 // when it carries its own key; moves from outside a row read key 0 and value
 // 0 (adding nothing), and rows a broadcast skips keep a key no row can have.
+// CTRL: a row shift, row_shr:n (0x110 + n) or row_shl:n (0x100 + n)
 template <int CTRL>
 __device__ inline uint32_t dpp_shr_u32(uint32_t v) {
     return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, CTRL, 0xf, 0xf, true);
@@ -210,11 +211,25 @@ __device__ inline float dpp_bcast(float v) {
 
 template <int CTRL, typename T, int KM>
 __device__ inline void scan_shr(uint32_t key, T (&v)[KM]) {
-    const bool take = dpp_shr_u32<CTRL>(key) == key;
+    if constexpr (sizeof(T) == 4) {
+        // FP32: each lane zeroes what the lane n places on in its row must
+        // not take (the row_shl:n move of the key gives that lane's key), so
+        // the move folds into a DPP add: two instructions per value, not
+        // three. The same terms are added in the same order.
+        constexpr int kShl = CTRL - 0x10;                     // row_shl:n for row_shr:n
+        const bool keep = dpp_shr_u32<kShl>(key) == key;
 #pragma unroll
-    for (int q = 0; q < KM; ++q) {
-        const T m = dpp_shr<CTRL>(v[q]);
-        v[q] += take ? m : T(0);
+        for (int q = 0; q < KM; ++q) {
+            const T w = keep ? v[q] : T(0);
+            v[q] += dpp_shr<CTRL>(w);
+        }
+    } else {
+        const bool take = dpp_shr_u32<CTRL>(key) == key;
+#pragma unroll
+        for (int q = 0; q < KM; ++q) {
+            const T m = dpp_shr<CTRL>(v[q]);
+            v[q] += take ? m : T(0);
+        }
     }
 }
 template <int CTRL, int RMASK, typename T, int KM>
