@@ -248,10 +248,14 @@ mxe_status mxe_scatter_y(mxe_ctx *ctx, mxe_mat b, int32_t k, const void *Yp, int
 mxe_status mxe_probe_gather(mxe_ctx *ctx, int64_t table_bytes, int64_t gathers, int32_t per_xcd,
                             void *stream, double *gathers_per_s);
 
-/* Times the candidate variants for (m, k) on the device and caches the
- * fastest; returns it in *variant (may be NULL). Synchronizes. */
+/* Times the candidate variants for (m, k) on the device (each briefly, then
+ * the closest few again, interleaved) and caches the fastest; returns it in
+ * *variant (may be NULL). Synchronizes. */
 mxe_status mxe_tune(mxe_ctx *ctx, mxe_mat m, int32_t k, void *stream, int32_t *variant);
-/* Forces a variant for (m, k); variant 0 clears the choice (retune on use). */
+/* Forces a variant for (m, k); variant 0 clears the choice (retune on use).
+ * MXE_ERR_INVALID_ARG for an unknown family, lanes out of range, or bits
+ * above the family; MXE_ERR_UNSUPPORTED when the variant cannot run on this
+ * matrix (a slab layout that does not fit, merge-path with k > 4). */
 mxe_status mxe_set_variant(mxe_ctx *ctx, mxe_mat m, int32_t k, int32_t variant);
 
 /* --- batches: many matrices, one persistent launch ------------------------- */

@@ -1034,6 +1034,7 @@ mxe_status mxe_set_variant(mxe_ctx *ctx, mxe_mat m, int32_t k, int32_t variant) 
         ctx->tuned.erase(key);
         return MXE_OK;
     }
+    if (variant & ~0xfff) return fail(MXE_ERR_INVALID_ARG, "unknown variant");
     const int family = variant & 0xf00, lanes = variant & 0xff;
     const bool pow2 = lanes >= 1 && lanes <= 64 && (lanes & (lanes - 1)) == 0;
     if ((family == MXE_VAR_GROUP || family == MXE_VAR_FIXED) && !pow2)

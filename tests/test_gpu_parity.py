@@ -476,8 +476,10 @@ def test_semiring_products_bit_exact(ctx, name, make, k):
     rperm, cperm = ctx.get_permutation(B)
     Bo = synth.CSR(A0.nrows, A0.ncols, *oracle.permute_csr(A0, rperm, cperm))
     shape = (A0.nrows, k) if k > 1 else (A0.nrows,)
-    # the tuned kernel, then the column-slab kernel forced (64 KiB and 2 MiB slabs)
-    for v in (None, mx.variant(mx.VAR_SLAB, 1), mx.variant(mx.VAR_SLAB, 32)):
+    # the tuned kernel, then the column-slab kernel forced (64 KiB and 2 MiB slabs, and
+    # 1 MiB slabs with row blocks for one workgroup per CU)
+    for v in (None, mx.variant(mx.VAR_SLAB, 1), mx.variant(mx.VAR_SLAB, 32),
+              mx.variant(mx.VAR_SLAB, 16 | mx.SLAB_ONE_PER_CU)):
         if v is not None and not (_force(ctx, A, k, v) and _force(ctx, B, k, v)):
             continue
         for sr in (mx.SR_MIN_PLUS, mx.SR_OR_AND):
@@ -512,6 +514,23 @@ def test_semiring_products_reduced_storage(ctx, storage):
             assert np.array_equal(np.isinf(got), np.isinf(ref))
             fin = np.isfinite(ref)
             assert np.all(np.abs(got[fin] - ref[fin]) <= 2.0 ** -23 * (np.abs(ref[fin]) + 2.0))
+    ctx.release(A)
+
+
+def test_set_variant_validates(ctx):
+    """Forced variants are checked before use: lane counts, families and slab
+    sizes (with or without the one-workgroup-per-CU flag)."""
+    A = ctx.register(synth.config1(1))
+    for bad in (mx.variant(mx.VAR_GROUP, 3), mx.variant(mx.VAR_GROUP, 128), 0x900,
+                mx.variant(mx.VAR_SLAB, 0), mx.variant(mx.VAR_SLAB, 65),
+                mx.variant(mx.VAR_SLAB, mx.SLAB_ONE_PER_CU),
+                mx.variant(mx.VAR_SLAB, 65 | mx.SLAB_ONE_PER_CU), 0x1301, -1):
+        with pytest.raises(mx.MxeError) as e:
+            ctx.set_variant(A, 1, bad)
+        assert e.value.status == mx.ERR_INVALID_ARG, hex(bad)
+    for good in (mx.variant(mx.VAR_SLAB, 1), mx.variant(mx.VAR_SLAB, 1 | mx.SLAB_ONE_PER_CU),
+                 mx.variant(mx.VAR_GROUP, 64)):
+        ctx.set_variant(A, 1, good)
     ctx.release(A)
 
 
