@@ -39,21 +39,29 @@ def spmv_bytes(nrows, ncols, nnz, val_bytes, vec_bytes, k=1):
 
 
 def kernel_source_hash(variant_hex: str = "0x300") -> str:
-    """Hash of the sources the measured SpMV kernel is built from: its kernel
+    """Hash of the code the measured SpMV kernel is built from: its kernel
     file and device body (column-slab or row kernels), the shared device
-    helpers and, for the slab kernel, its layout descriptor."""
+    helpers and, for the slab kernel, its layout descriptor. Comments and
+    whitespace are left out, so only a change to the code itself voids a
+    traffic measurement."""
     import re
+
+    def code(text: str) -> bytes:
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        return " ".join(text.split()).encode()
+
     csrc = os.path.join(ROOT, "paper_2308_00106_amd", "csrc")
     slab = (int(variant_hex, 16) & 0xf00) == 0x300
     h = hashlib.sha256()
     files = ("kernels_slab.hip", "slab_device.h") if slab else ("kernels_spmv.hip", "spmv_device.h")
     for f in (*files, "device_common.h"):
-        with open(os.path.join(csrc, f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(csrc, f)) as fh:
+            h.update(code(fh.read()))
     if slab:
         with open(os.path.join(csrc, "internal.h")) as fh:
             m = re.search(r"struct SlabGeom \{.*?\};", fh.read(), re.S)
-        h.update(m.group(0).encode() if m else b"")
+        h.update(code(m.group(0)) if m else b"")
     return h.hexdigest()[:16]
 
 

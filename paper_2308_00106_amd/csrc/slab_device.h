@@ -26,15 +26,17 @@ template <> struct SlabVal<uint16_t, float> {
     __device__ static float get(uint16_t v) { return bf16_to_f32(v); }
 };
 
-// Block `block` of the layout, by a workgroup of kSlabBlock threads on XCD
-// `xcd`; tid is the thread's index in it. yp: LDS for the block's partial y (rows_per_block x KM values of T);
-// soff: LDS for the wavefronts' group offsets. The workgroup walks the slabs
-// in its rotation together (a barrier after each slab), starting at a slab
-// tied to its XCD, so all its wavefronts gather from the same L2-resident x
-// slice; inside a slab a wavefront loads up to SlabUnroll chunks of its group
-// at once, issues their x gathers together, then reduces each chunk by row.
-// The first batch of the next slab's group is loaded before each barrier.
-// The caller separates two calls on one workgroup by a barrier.
+// Block `block` of the layout, by a workgroup of kSlabBlock threads; tid is
+// the thread's index in it. The workgroup walks the slabs in a rotation that
+// starts at the slab tied to XCD `xcd` (its own XCD; in a batch, the XCD of
+// the queue the block came from), all together (a barrier after each slab),
+// so its wavefronts gather from the same L2-resident x slice; inside a slab a
+// wavefront loads up to SlabUnroll chunks of its group at once, issues their x
+// gathers together, then reduces each chunk by row. The first batch of the
+// next slab's group is loaded before each barrier. yp: LDS for the block's
+// partial y (rows_per_block x KM values of T); soff: LDS for the wavefronts'
+// group offsets; vec_x: X rows are read as 16-byte vectors (slab_vec_x). The
+// caller separates two calls on one workgroup by a barrier.
 template <typename V, typename T, int KM, int SR>
 __device__ __attribute__((always_inline)) inline void
 slab_block(const SlabGeom &g, int32_t block, int xcd, const int32_t *__restrict__ off,
