@@ -35,6 +35,31 @@ def test_header_declares_the_boundary():
         assert n in names
 
 
+def test_binding_constants_match_the_header():
+    """Every numeric #define of the header (flags, semirings, variant
+    families) has the same value in the binding, under its name without the
+    MXE_ prefix."""
+    text = open(HEADER).read()
+    defs = dict(re.findall(r"#define MXE_([A-Z0-9_]+)\s+(0x[0-9a-fA-F]+|[0-9]+)u?\b", text))
+    skip = {"ABI_VERSION"}
+    checked = 0
+    for name, value in defs.items():
+        if name in skip:
+            continue
+        assert hasattr(mx, name), name
+        assert getattr(mx, name) == int(value, 0), (name, value)
+        checked += 1
+    assert checked >= 15
+    # the status and storage enumerations, value by value
+    enums = re.findall(r"typedef enum \w*\s*\{(.*?)\}", text, re.S)
+    assert len(enums) >= 2
+    for enum in enums:
+        names = re.findall(r"\bMXE_([A-Z0-9_]+)\s*=\s*([0-9]+)", enum)
+        assert names
+        for name, value in names:
+            assert getattr(mx, name) == int(value), name
+
+
 def test_every_declared_symbol_is_exported(lib):
     missing = [n for n in _declared() if not hasattr(lib, n)]
     assert not missing, missing
