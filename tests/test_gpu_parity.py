@@ -332,6 +332,15 @@ def test_full_size_config2(ctx):
         ctx.spmv(H, xt, y)
         torch.cuda.synchronize()
         assert spmv_error(Ho, x, y.cpu().numpy(), "f64") <= 1e-13
+    # every slab layout the tuner picks for this workload on some box, forced
+    for v in (mx.variant(mx.VAR_SLAB, 12), mx.variant(mx.VAR_SLAB, 16 | mx.SLAB_ONE_PER_CU),
+              mx.variant(mx.VAR_SLAB, 20 | mx.SLAB_ONE_PER_CU),
+              mx.variant(mx.VAR_SLAB, 24 | mx.SLAB_ONE_PER_CU)):
+        ctx.set_variant(B, 1, v)
+        y = torch.full((A0.nrows,), float("nan"), dtype=torch.float64, device="cuda")
+        ctx.spmv(B, xt, y)
+        torch.cuda.synchronize()
+        assert spmv_error(Bo, x, y.cpu().numpy(), "f64") <= 1e-13, hex(v)
     ctx.release(B)
     ctx.release(A)
 
