@@ -1,7 +1,8 @@
 """GPU parity at the workloads' full sizes, in the launch configurations the
-benchmark times (autotuned variants, persistent batch plan): the skewed
-4,000,000-row matrix in FP64 / FP32 / BF16 storage and the 64-matrix batch.
-Every output element is compared with the oracle."""
+benchmark times (autotuned variants, persistent batch plan, serving loop):
+the skewed 4,000,000-row matrix in FP64 / FP32 / BF16 storage, the 64-matrix
+batch and requests on full-size serving-pool matrices. Every output element
+is compared with the oracle."""
 import numpy as np
 import pytest
 
@@ -90,5 +91,38 @@ def test_batch_full_size(ctx):
         err = spmv_error(Bo, X, Y.cpu().numpy().astype(np.float64), "f32")
         assert err <= TOL["f32"], (i, err)
     ctx.batch_destroy(plan)
+    for H in hs:
+        ctx.release(H)
+
+
+def test_serving_full_size(ctx):
+    """The serving loop on full-size pool matrices (block-clustered and skewed,
+    up to 1.76M rows, FP32) in the benchmark's configuration (4 streams, 32 in
+    flight, merging up to k = 16): 48 requests of k = 1..8 submitted at once,
+    every output checked against the FP64 oracle."""
+    pool = [synth.config5(i) for i in (0, 1, 2, 3, 5)]
+    print("serving pool rows", [A.nrows for A in pool], flush=True)
+    hs = [ctx.permute(ctx.register(A, "f32"), 1000 + i) for i, A in enumerate(pool)]
+    Bo = []
+    for H, A0 in zip(hs, pool):
+        rperm, cperm = ctx.get_permutation(H)
+        Bo.append(synth.CSR(A0.nrows, A0.ncols, *oracle.permute_csr(A0, rperm, cperm)))
+    rng = np.random.default_rng(17)
+    reqs = []
+    for i in range(48):
+        m = int(rng.integers(0, len(pool)))
+        k = int(rng.integers(1, 9))
+        X = synth.vector(pool[m].ncols, 300 + i, k=k) if k > 1 else synth.vector(pool[m].ncols, 300 + i)
+        Y = torch.full((pool[m].nrows, k) if k > 1 else (pool[m].nrows,), float("nan"),
+                       dtype=torch.float32, device="cuda")
+        reqs.append((m, X, torch_vec(X, torch.float32), Y))
+    ctx.serve_start(streams=4, max_inflight=32, max_merge_k=16)
+    tickets = [ctx.submit(hs[m], Xd, Y) for m, _, Xd, Y in reqs]
+    for t in tickets:
+        ctx.wait(t)
+    ctx.serve_stop()
+    for i, (m, X, _, Y) in enumerate(reqs):
+        err = spmv_error(Bo[m], X, Y.cpu().numpy().astype(np.float64), "f32")
+        assert err <= TOL["f32"], (i, m, err)
     for H in hs:
         ctx.release(H)
