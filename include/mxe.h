@@ -148,11 +148,10 @@ mxe_status mxe_export_csr(mxe_ctx *ctx, mxe_mat m, int32_t *row_ptr, int32_t *co
 mxe_status mxe_matrix_info(mxe_ctx *ctx, mxe_mat m, mxe_matrix_desc *out);
 
 /* Releases a handle. A permuted matrix keeps its parent's memory until it is
- * released too. Returns MXE_ERR_BUSY while serving work on it is queued or
- * running. When the last handle to a matrix's memory goes, the call waits for
- * the device to finish all queued work (on any stream) before freeing it, so
- * work already enqueued on the matrix completes safely; batch plans that name
- * the matrix must be destroyed first. */
+ * released too, and a batch plan keeps its matrices' memory until the plan is
+ * destroyed. Returns MXE_ERR_BUSY while serving work on it is queued or
+ * running. When the last reference to a matrix's memory goes, the device
+ * finishes all queued work (on any stream) before the memory is freed. */
 mxe_status mxe_release(mxe_ctx *ctx, mxe_mat m);
 
 /* --- measure (Sections 4 and 5) --------------------------------------------- */

@@ -1210,6 +1210,7 @@ mxe_status mxe_batch_create(mxe_ctx *ctx, int32_t count, const mxe_item *items, 
     plan->grid = batch_grid_size(plan->vtype, plan->lds);
     if (plan->grid < 1) return fail(MXE_ERR_DEVICE, "batch kernel occupancy query failed");
     plan->items.assign(items, items + count);
+    for (int32_t i = 0; i < count; ++i) plan->mats.push_back(find_matrix(ctx, items[i].mat));
     MXE_HIP(hipMalloc(&plan->descs_dev, sizeof(BatchDesc) * plan->descs.size()));
     MXE_HIP(hipMalloc(&plan->counters, sizeof(int32_t) * (kBatchQueues + plan->qent.size())));
     MXE_HIP(hipMemcpy(plan->descs_dev, plan->descs.data(), sizeof(BatchDesc) * plan->descs.size(),
@@ -1251,9 +1252,8 @@ mxe_status mxe_batch_launch(mxe_ctx *ctx, mxe_plan h, const mxe_item *items, voi
             const mxe_item &a = items[i], &b = p.items[i];
             if (a.mat != b.mat || a.k != b.k || a.flags != b.flags)
                 return fail(MXE_ERR_INVALID_ARG, "batch items differ from the plan's matrices or k");
-            auto A = find_matrix(ctx, a.mat);
-            if (!A) return fail(MXE_ERR_NOT_FOUND, "unknown matrix handle in batch");
-            mxe_status st = check_dense(*A, a.k, a.X, a.ldx, a.Y, a.ldy);
+            // the plan's own reference: valid even after the handle was released
+            mxe_status st = check_dense(*p.mats[i], a.k, a.X, a.ldx, a.Y, a.ldy);
             if (st) return st;
         }
         bool changed = false;

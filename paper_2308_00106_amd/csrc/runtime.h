@@ -80,6 +80,7 @@ struct TuneResult { int variant; int group_lanes; };
 
 struct Plan {
     std::vector<mxe_item> items;
+    std::vector<std::shared_ptr<Matrix>> mats;   // kept alive while the plan exists
     std::vector<BatchDesc> descs;
     BatchDesc *descs_dev = nullptr;
     std::vector<int32_t> qent;          // per-XCD queue entries (desc indices)

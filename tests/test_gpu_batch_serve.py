@@ -79,7 +79,8 @@ def test_batch_uneven_multi_rhs(ctx):
 
 def test_batch_plan_graph_replays(ctx):
     """The plan's graph replays correctly several times, with eager work and
-    synchronisation between replays and with new X / Y buffers."""
+    synchronisation between replays, with new X / Y buffers, and after its
+    matrices' handles are released (the plan keeps them alive)."""
     mats = _pool(5, 200)
     ks = [1, 4, 16, 2, 8]
     handles = [ctx.permute(ctx.register(A, "f32"), 9) for A in mats]
@@ -110,6 +111,16 @@ def test_batch_plan_graph_replays(ctx):
             assert spmv_error(Bo, X, Y.cpu().numpy().astype(np.float64), "f32") <= TOL["f32"]
     with pytest.raises(mx.MxeError):
         ctx.batch_launch(plan, list(zip(handles[::-1], Xt2[::-1], Ys2[::-1])))
+    # the plan keeps its matrices alive: released handles still replay, with
+    # the planned vectors and with new ones
+    for H in handles:
+        ctx.release(H)
+    for Y in Ys2:
+        Y.fill_(float("nan"))
+    ctx.batch_launch(plan)
+    torch.cuda.synchronize()
+    for Bo, X, Y in zip(B0, Xs2, Ys2):
+        assert spmv_error(Bo, X, Y.cpu().numpy().astype(np.float64), "f32") <= TOL["f32"]
     ctx.batch_destroy(plan)
 
 
