@@ -543,14 +543,6 @@ mxe_status mxe_destroy(mxe_ctx *ctx) {
         std::lock_guard<std::recursive_mutex> lk(ctx->mu);
         DeviceGuard g(ctx->device);
         (void)hipDeviceSynchronize();
-        for (auto &kv : ctx->plans) {
-            Plan &p = *kv.second;
-            if (p.exec) (void)hipGraphExecDestroy(p.exec);
-            if (p.graph) (void)hipGraphDestroy(p.graph);
-            if (p.capture_stream) (void)hipStreamDestroy(p.capture_stream);
-            if (p.descs_dev) (void)hipFree(p.descs_dev);
-            if (p.counters) (void)hipFree(p.counters);
-        }
         ctx->plans.clear();
         ctx->mats.clear();
     }
@@ -1224,14 +1216,8 @@ mxe_status mxe_batch_create(mxe_ctx *ctx, int32_t count, const mxe_item *items, 
     hipError_t e2 = launch_spmv_batch(plan->descs_dev, plan->counters + kBatchQueues, plan->queues,
                                       plan->counters, plan->grid, plan->lds, plan->vtype, cs);
     hipError_t e3 = hipStreamEndCapture(cs, &plan->graph);
-    if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) {
-        Plan &p = *plan;
-        if (p.graph) (void)hipGraphDestroy(p.graph);
-        (void)hipStreamDestroy(p.capture_stream);
-        (void)hipFree(p.descs_dev);
-        (void)hipFree(p.counters);
+    if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess)   // ~Plan frees what was made
         return hip_fail(e1 != hipSuccess ? e1 : e2 != hipSuccess ? e2 : e3, "batch graph capture");
-    }
     MXE_HIP(hipGraphInstantiate(&plan->exec, plan->graph, nullptr, nullptr, 0));
     const int64_t id = ctx->next_id++;
     ctx->plans[id] = std::move(plan);
@@ -1288,13 +1274,7 @@ mxe_status mxe_batch_destroy(mxe_ctx *ctx, mxe_plan h) {
     DeviceGuard g(ctx->device);
     auto it = ctx->plans.find(h);
     if (it == ctx->plans.end()) return fail(MXE_ERR_NOT_FOUND, "unknown plan handle");
-    Plan &p = *it->second;
-    (void)hipDeviceSynchronize();
-    if (p.exec) (void)hipGraphExecDestroy(p.exec);
-    if (p.graph) (void)hipGraphDestroy(p.graph);
-    if (p.capture_stream) (void)hipStreamDestroy(p.capture_stream);
-    (void)hipFree(p.descs_dev);
-    (void)hipFree(p.counters);
+    (void)hipDeviceSynchronize();                   // replays finish before ~Plan frees
     ctx->plans.erase(it);
     return MXE_OK;
 }

@@ -92,6 +92,20 @@ struct Plan {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     hipStream_t capture_stream = nullptr;
+
+    Plan() = default;
+    Plan(const Plan &) = delete;
+    Plan &operator=(const Plan &) = delete;
+    // Frees what the plan holds, whatever step of its creation it reached.
+    // The caller has the plan's device current and its replays finished; the
+    // matrix references go after the graph (members are destroyed after the body).
+    ~Plan() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (capture_stream) (void)hipStreamDestroy(capture_stream);
+        if (descs_dev) (void)hipFree(descs_dev);
+        if (counters) (void)hipFree(counters);
+    }
 };
 
 struct Server;
