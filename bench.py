@@ -29,7 +29,7 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 FP64_TOL = 1e-13               # max_i |y - y_ref| / (|A||x|)_i against the FP64 oracle
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "spmv_permuted_config2_traffic.txt")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "spmv_permuted_n2m_fp64_traffic.txt")
 
 
 def spmv_bytes(nrows, ncols, nnz, val_bytes, vec_bytes, k=1):
@@ -231,7 +231,7 @@ def main():
 
     n, reps, grid, seed = args.n, args.reps, 1024, 3
     t = time.perf_counter()
-    A0 = synth.config2(1, n=n)
+    A0 = synth.clustered_n2m(1, n=n)
     x = synth.vector(A0.ncols, 2)
     log(f"generated n={n} nnz={A0.nnz} in {time.perf_counter() - t:.1f}s")
     nbytes = spmv_bytes(A0.nrows, A0.ncols, A0.nnz, 8, 8)

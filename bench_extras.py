@@ -52,7 +52,7 @@ def skewed(ctx, log, n=4_000_000, reps=50):
     from paper_2308_00106_amd import mxe as mx
     stream = torch.cuda.current_stream()
     t = time.perf_counter()
-    A0 = synth.config3(1, n=n)
+    A0 = synth.skewed_n4m(1, n=n)
     x = synth.vector(A0.ncols, 2)
     log(f"skewed: generated n={n} nnz={A0.nnz} in {time.perf_counter() - t:.1f}s")
     yref = oracle.spmv(A0, x)
@@ -136,7 +136,7 @@ def semiring(ctx, log, n=2_000_000, reps=50):
     import torch
     from paper_2308_00106_amd import mxe as mx
     stream = torch.cuda.current_stream()
-    A0 = synth.config2(1, n=n)
+    A0 = synth.clustered_n2m(1, n=n)
     A = ctx.register(A0)
     B = ctx.permute(A, 3, stream=stream)
     nb = _bytes(A0, 8, 8, 1)
@@ -170,7 +170,7 @@ def batch(ctx, log, count=64, replays=20):
     t = time.perf_counter()
     mats, ks = [], []
     for i in range(count):
-        A, k = synth.config4(i)
+        A, k = synth.batch_member(i)
         mats.append(A)
         ks.append(k)
     log(f"batch: generated {count} matrices, {sum(A.nnz for A in mats)} nnz in "
@@ -226,7 +226,7 @@ def serving(ctx_unused, log, pool=32, warm=1000, n_req=20000):
     import torch
     from paper_2308_00106_amd import mxe as mx
     t = time.perf_counter()
-    mats = [synth.config5(i) for i in range(pool)]
+    mats = [synth.serving_member(i) for i in range(pool)]
     log(f"serving: generated {pool} matrices, {sum(A.nrows for A in mats)} rows, "
         f"{sum(A.nnz for A in mats)} nnz in {time.perf_counter() - t:.1f}s")
     budget = 200 * (1 << 30)

@@ -20,7 +20,7 @@ import numpy as np
 
 __all__ = [
     "CSR", "from_entries", "block_clustered", "skewed_clustered", "heavy_clustered",
-    "config1", "config2", "config3", "config4", "config5",
+    "clustered_n4096", "clustered_n2m", "skewed_n4m", "batch_member", "serving_member",
     "random_csr", "vector", "uniform_fill",
 ]
 
@@ -170,21 +170,21 @@ def vector(n: int, seed: int, k: int = 1) -> np.ndarray:
     return v[:, 0].copy() if k == 1 else v
 
 
-# --- the five workload configurations ---------------------------------------
+# --- the five workloads ----------------------------------------------------
 
-def config1(seed: int = 1) -> CSR:
+def clustered_n4096(seed: int = 1) -> CSR:
     """n = 4096, 16 nnz per row, 90% (in expectation) inside the row's own
     64-wide diagonal block, the rest uniform outside it."""
     return block_clustered(4096, 16, 64, 0.9, seed)
 
 
-def config2(seed: int = 1, n: int = 2_000_000) -> CSR:
+def clustered_n2m(seed: int = 1, n: int = 2_000_000) -> CSR:
     """n = 2,000,000, 10 nnz per row, 90% (in expectation) inside the
     4096-row diagonal block, the rest uniform outside it."""
     return block_clustered(n, 10, 4096, 0.9, seed)
 
 
-def config3(seed: int = 1, n: int = 4_000_000) -> CSR:
+def skewed_n4m(seed: int = 1, n: int = 4_000_000) -> CSR:
     """n = 4,000,000, row lengths lognormal(mu=2, sigma=1) capped at 256,
     columns Gaussian (sigma = 2000) around the row index."""
     return skewed_clustered(n, 2.0, 1.0, 256, 2000.0, seed)
@@ -193,7 +193,7 @@ def config3(seed: int = 1, n: int = 4_000_000) -> CSR:
 BATCH_K = (1, 2, 4, 8, 16)
 
 
-def config4(index: int, seed_base: int = 1000) -> tuple[CSR, int]:
+def batch_member(index: int, seed_base: int = 1000) -> tuple[CSR, int]:
     """Matrix `index` of the 64-matrix batch: rows log-uniform in
     [10k, 500k], 8-32 nnz per row, 90% inside 4096-row diagonal blocks.
     Returns the matrix and its right-hand-side count k."""
@@ -205,7 +205,7 @@ def config4(index: int, seed_base: int = 1000) -> tuple[CSR, int]:
     return block_clustered(n, lens, 4096, 0.9, seed), k
 
 
-def config5(index: int, seed_base: int = 1000) -> CSR:
+def serving_member(index: int, seed_base: int = 1000) -> CSR:
     """Matrix `index` of the 32-matrix serving pool: rows log-uniform in
     [50k, 2M]; even indices take the block-clustered structure, odd ones the
     skewed clustered structure."""

@@ -77,7 +77,7 @@ def _v(nrows, ncols, rp, col):
 
 
 def test_validate_accepts_canonical_csr(lib):
-    A = synth.config1(1)
+    A = synth.clustered_n4096(1)
     assert _v(A.nrows, A.ncols, A.row_ptr, A.col) == mx.OK
     assert _v(0, 0, [0], []) == mx.OK
     assert _v(3, 5, [0, 0, 0, 0], []) == mx.OK           # empty rows

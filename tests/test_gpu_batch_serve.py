@@ -185,7 +185,7 @@ def test_batch_slab_layout_within_budget():
     """A batch gives a slab-tuned item a second layout with row blocks sized
     for one XCD; when the HBM budget has no room for it the item runs on its
     tuned layout, with a correct result either way."""
-    A0 = synth.config2(1, n=200_000)
+    A0 = synth.clustered_n2m(1, n=200_000)
     k = 4
     X = synth.vector(A0.ncols, 6, k=k)
 
@@ -299,7 +299,7 @@ def test_serving_mix_matches_alone(ctx):
 
 
 def test_serving_budget_admission_and_busy_release(ctx):
-    A0 = synth.config2(1, n=200_000)
+    A0 = synth.clustered_n2m(1, n=200_000)
     with mx.Context(0, budget_bytes=0) as probe:
         H = probe.register(A0, "f32")
         resident = probe.matrix_info(H).device_bytes
@@ -331,7 +331,7 @@ def test_serving_budget_admission_and_busy_release(ctx):
 
 
 def test_wait_timeout_and_unknown_ticket(ctx):
-    A0 = synth.config2(1, n=100_000)
+    A0 = synth.clustered_n2m(1, n=100_000)
     H = ctx.register(A0, "f32")
     ctx.serve_start(streams=1, max_inflight=1, max_merge_k=1)
     X = torch_vec(synth.vector(A0.ncols, 3), torch.float32)

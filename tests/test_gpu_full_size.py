@@ -27,7 +27,7 @@ def ctx():
 
 @pytest.fixture(scope="module")
 def skewed():
-    return synth.config3(1)
+    return synth.skewed_n4m(1)
 
 
 def test_skewed_full_size_permutation_csr_entropy(ctx, skewed):
@@ -73,7 +73,7 @@ def test_skewed_full_size_spmv(ctx, skewed, storage):
 def test_batch_full_size(ctx):
     """The 64-matrix batch (119M nonzeros, k in {1, 2, 4, 8, 16}, FP32) as one
     persistent launch replayed from a HIP graph, every output checked."""
-    mats, ks = zip(*(synth.config4(i) for i in range(64)))
+    mats, ks = zip(*(synth.batch_member(i) for i in range(64)))
     print(f"batch nnz={sum(A.nnz for A in mats)}", flush=True)
     hs = [ctx.permute(ctx.register(A, "f32"), 1000 + i) for i, A in enumerate(mats)]
     Xs = [synth.vector(A.ncols, 50 + i, k=k) if k > 1 else synth.vector(A.ncols, 50 + i)
@@ -100,7 +100,7 @@ def test_serving_full_size(ctx):
     up to 1.76M rows, FP32) in the benchmark's configuration (4 streams, 32 in
     flight, merging up to k = 16): 48 requests of k = 1..8 submitted at once,
     every output checked against the FP64 oracle."""
-    pool = [synth.config5(i) for i in (0, 1, 2, 3, 5)]
+    pool = [synth.serving_member(i) for i in (0, 1, 2, 3, 5)]
     print("serving pool rows", [A.nrows for A in pool], flush=True)
     hs = [ctx.permute(ctx.register(A, "f32"), 1000 + i) for i, A in enumerate(pool)]
     Bo = []

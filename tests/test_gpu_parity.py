@@ -80,12 +80,12 @@ def test_permute_modes_identity_parts(ctx):
 # --- permuted CSR ---------------------------------------------------------------
 
 CSR_CASES = [
-    ("config1", lambda: synth.config1(1)),
+    ("clustered_n4096", lambda: synth.clustered_n4096(1)),
     ("ragged", lambda: synth.random_csr(4096 * 3 + 17, 9001, 0.002, 2, empty_rows=0.1)),
     ("wide", lambda: synth.random_csr(333, 20000, 0.01, 3)),
     ("long_rows", lambda: synth.random_csr(700, 3000, 0.15, 4)),     # rows > 256: global path
     ("empty", lambda: synth.random_csr(50, 60, 0.0, 5)),
-    ("skewed", lambda: synth.config3(1, n=60_000)),
+    ("skewed", lambda: synth.skewed_n4m(1, n=60_000)),
 ]
 
 
@@ -121,8 +121,8 @@ def test_registered_values_round_once(ctx):
 
 # --- histogram and entropy -----------------------------------------------------
 
-@pytest.mark.parametrize("case,grid", [("config1", (64, 64)), ("config1", (1, 1)),
-                                       ("config1", (7, 3)), ("config1", (4096, 1)),
+@pytest.mark.parametrize("case,grid", [("clustered_n4096", (64, 64)), ("clustered_n4096", (1, 1)),
+                                       ("clustered_n4096", (7, 3)), ("clustered_n4096", (4096, 1)),
                                        ("ragged", (64, 64)), ("wide", (5, 1000)),
                                        ("skewed", (1024, 1024)), ("skewed", (3, 20000))])
 def test_histogram_and_entropy_exact(ctx, case, grid):
@@ -149,8 +149,8 @@ def test_entropy_uniform_fill_and_single_block(ctx):
     ctx.release(E)
 
 
-def test_entropy_permuted_config1(ctx):
-    A0 = synth.config1(1)
+def test_entropy_permuted_clustered_n4096(ctx):
+    A0 = synth.clustered_n4096(1)
     A = ctx.register(A0)
     B = ctx.permute(A, 3)
     h0, h1 = ctx.entropy(A, 64, 64)[0], ctx.entropy(B, 64, 64)[0]
@@ -160,7 +160,7 @@ def test_entropy_permuted_config1(ctx):
 
 
 def test_entropy_rejects_bad_grid(ctx):
-    A = ctx.register(synth.config1(1))
+    A = ctx.register(synth.clustered_n4096(1))
     for g in ((0, 4), (4, 0), (2**20 + 1, 1)):
         with pytest.raises(mx.MxeError) as e:
             ctx.entropy(A, *g)
@@ -239,7 +239,7 @@ def test_spmv_reduced_precision(ctx, storage, name, make):
 def test_identity_original_space(ctx):
     """y = P_r^-1 ((P_r A P_c)(P_c^-1 x)) equals A x (Eq. 1), via the
     original-space flag and via explicit gather / scatter."""
-    A0 = synth.config1(1)
+    A0 = synth.clustered_n4096(1)
     x = synth.vector(A0.ncols, 2)
     A = ctx.register(A0)
     B = ctx.permute(A, 3)
@@ -265,7 +265,7 @@ def test_identity_original_space(ctx):
 @pytest.mark.parametrize("k", [1, 5, 16])
 def test_every_variant_is_bitwise_repeatable(ctx, k):
     """Each variant sums every row in a fixed order: two runs give the same bits."""
-    A0 = synth.config3(1, n=60_000)
+    A0 = synth.skewed_n4m(1, n=60_000)
     A = ctx.register(A0)
     B = ctx.permute(A, 4)
     X = torch_vec(synth.vector(A0.ncols, 2, k=k), torch.float64)
@@ -285,7 +285,7 @@ def test_every_variant_is_bitwise_repeatable(ctx, k):
 
 
 def test_runs_are_bitwise_deterministic(ctx):
-    A0 = synth.config3(1, n=40_000)
+    A0 = synth.skewed_n4m(1, n=40_000)
     A = ctx.register(A0)
     x = torch_vec(synth.vector(A0.ncols, 2), torch.float64)
     outs = []
@@ -306,10 +306,10 @@ def test_runs_are_bitwise_deterministic(ctx):
 
 # --- full-size configuration, as the benchmark runs it ------------------------------
 
-def test_full_size_config2(ctx):
+def test_full_size_clustered_n2m(ctx):
     """n = 2,000,000 block-clustered matrix: permutation, permuted CSR,
     1024 x 1024 entropy and the tuned SpMV against the oracle in full."""
-    A0 = synth.config2(1)
+    A0 = synth.clustered_n2m(1)
     x = synth.vector(A0.ncols, 2)
     A = ctx.register(A0)
     B = ctx.permute(A, 3)
@@ -347,7 +347,7 @@ def test_full_size_config2(ctx):
 
 # --- hierarchical entropy, gradient formats, fixed partition ------------------------
 
-@pytest.mark.parametrize("case,grid", [("config1", (64, 64)), ("skewed", (64, 64)),
+@pytest.mark.parametrize("case,grid", [("clustered_n4096", (64, 64)), ("skewed", (64, 64)),
                                        ("wide", (5, 1000)), ("ragged", (37, 23)),
                                        ("skewed", (1024, 1024))])    # several workgroups a region
 def test_entropy_levels_exact(ctx, case, grid):
@@ -435,7 +435,7 @@ def test_coo_rows_across_many_tiles(ctx):
 def test_tuning_keeps_only_the_chosen_slab_layout(ctx):
     """The autotuner times several column-slab layouts; afterwards the matrix
     holds at most the one it chose (HBM accounting)."""
-    A0 = synth.config2(1, n=600_000)
+    A0 = synth.clustered_n2m(1, n=600_000)
     A = ctx.register(A0)
     B = ctx.permute(A, 3)
     before = ctx.matrix_info(B).device_bytes
@@ -505,7 +505,7 @@ def test_semiring_products_bit_exact(ctx, name, make, k):
 
 @pytest.mark.parametrize("storage", ["f32", "bf16"])
 def test_semiring_products_reduced_storage(ctx, storage):
-    A0 = synth.config3(1, n=50_000)
+    A0 = synth.skewed_n4m(1, n=50_000)
     X = _semiring_x(A0.ncols, 4, 8)
     X32 = X.astype(np.float32).astype(np.float64)
     A = ctx.register(A0, storage)
@@ -529,7 +529,7 @@ def test_semiring_products_reduced_storage(ctx, storage):
 def test_set_variant_validates(ctx):
     """Forced variants are checked before use: lane counts, families and slab
     sizes (with or without the one-workgroup-per-CU flag)."""
-    A = ctx.register(synth.config1(1))
+    A = ctx.register(synth.clustered_n4096(1))
     for bad in (mx.variant(mx.VAR_GROUP, 3), mx.variant(mx.VAR_GROUP, 128), 0x900,
                 mx.variant(mx.VAR_SLAB, 0), mx.variant(mx.VAR_SLAB, 65),
                 mx.variant(mx.VAR_SLAB, mx.SLAB_ONE_PER_CU),
@@ -544,7 +544,7 @@ def test_set_variant_validates(ctx):
 
 
 def test_semiring_rejects_unknown(ctx):
-    A = ctx.register(synth.config1(1))
+    A = ctx.register(synth.clustered_n4096(1))
     x = torch.zeros(4096, dtype=torch.float64, device="cuda")
     y = torch.zeros(4096, dtype=torch.float64, device="cuda")
     with pytest.raises(mx.MxeError) as e:

@@ -249,7 +249,7 @@ def test_entropy_rises_after_permutation():
     """Sanity: the block-clustered matrix's entropy rises towards log2(4096)
     once permuted (analytic expectation for a random placement of S entries
     in B bins: log2 B - (B-1)/(2 S ln 2) to first order)."""
-    A = synth.config1(1)
+    A = synth.clustered_n4096(1)
     h0 = oracle.block_hist(A.nrows, A.ncols, A.row_ptr, A.col, 64, 64)
     _, _, (rp, col, _) = oracle.permute(A, 3)
     h1 = oracle.block_hist(A.nrows, A.ncols, rp, col, 64, 64)
@@ -376,7 +376,7 @@ def test_spmm_parallel_equals_serial():
 
 def test_permuted_product_identity():
     """y = P_r^-1 ((P_r A P_c)(P_c^-1 x)) equals A x (Eq. 1)."""
-    A = synth.config1(1)
+    A = synth.clustered_n4096(1)
     x = synth.vector(A.ncols, 2)
     rperm, cperm, B = oracle.permute(A, 3)
     y = oracle.permuted_spmm(A, rperm, cperm, B, x)

@@ -13,20 +13,20 @@ def _canonical(A):
     assert np.all(np.diff(A.col.astype(np.int64))[same] > 0)
 
 
-def test_config1_structure():
-    A = synth.config1(1)
+def test_clustered_n4096_structure():
+    A = synth.clustered_n4096(1)
     _canonical(A)
     assert A.nrows == A.ncols == 4096 and np.all(A.row_lengths() == 16)
     rows = np.repeat(np.arange(4096), 16)
     frac = np.mean(A.col // 64 == rows // 64)
     assert abs(frac - 0.9) < 0.005          # Binomial(16, 0.9) per row
     assert np.all(np.abs(A.val) <= 1)
-    B = synth.config1(1)
+    B = synth.clustered_n4096(1)
     assert np.array_equal(A.col, B.col) and np.array_equal(A.val, B.val)
 
 
-def test_config2_structure_small():
-    A = synth.config2(1, n=100_000)
+def test_clustered_n2m_structure_small():
+    A = synth.clustered_n2m(1, n=100_000)
     _canonical(A)
     assert np.all(A.row_lengths() == 10)
     rows = np.repeat(np.arange(A.nrows), 10)
@@ -34,8 +34,8 @@ def test_config2_structure_small():
     assert abs(frac - 0.9) < 0.003
 
 
-def test_config3_structure_small():
-    A = synth.config3(1, n=200_000)
+def test_skewed_n4m_structure_small():
+    A = synth.skewed_n4m(1, n=200_000)
     _canonical(A)
     L = A.row_lengths()
     assert L.min() >= 1 and L.max() <= 256
@@ -46,8 +46,8 @@ def test_config3_structure_small():
     assert abs(np.std(d[inner]) - 2000) < 40
 
 
-def test_config4_and_5_small_members():
-    A, k = synth.config4(0)
+def test_batch_and_serving_small_members():
+    A, k = synth.batch_member(0)
     _canonical(A)
     assert 10_000 <= A.nrows <= 500_000 and k in synth.BATCH_K
     L = A.row_lengths()
