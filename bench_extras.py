@@ -315,6 +315,44 @@ def serving(ctx_unused, log, pool=32, warm=1000, n_req=20000):
     return out
 
 
-def run_all(ctx, log):
-    return {"skewed": skewed(ctx, log), "heavy": heavy(ctx, log), "semiring": semiring(ctx, log),
-            "batch": batch(ctx, log), "serving": serving(ctx, log)}
+PARTS = {"skewed": skewed, "heavy": heavy, "semiring": semiring, "batch": batch, "serving": serving}
+
+
+def run_all(ctx, log, parts=tuple(PARTS)):
+    return {name: PARTS[name](ctx, log) for name in parts}
+
+
+def main(argv=None) -> int:
+    """`python bench_extras.py [part ...]`: the named parts alone (all by
+    default), one JSON line on stdout; used to profile one workload."""
+    import argparse
+    import json
+    import sys
+
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("parts", nargs="*", help="any of: " + ", ".join(PARTS))
+    args = ap.parse_args(argv)
+    unknown = [p for p in args.parts if p not in PARTS]
+    if unknown:
+        ap.error(f"unknown part(s) {unknown}; choose from {list(PARTS)}")
+    args.parts = args.parts or list(PARTS)
+
+    def log(msg):
+        print(f"[extras] {msg}", file=sys.stderr, flush=True)
+
+    import torch
+
+    import bench
+    from paper_2308_00106_amd import mxe as mx
+    ctx = mx.Context(0)
+    # first: a 1 GiB read and copy of known size, which also calibrates the
+    # FETCH_SIZE / WRITE_SIZE counters of a profiled run
+    out = {"hbm_ceiling_measured": bench.hbm_ceiling(torch.cuda.current_stream())}
+    log(f"hbm ceiling: {out['hbm_ceiling_measured']}")
+    out.update(run_all(ctx, log, args.parts))
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    raise SystemExit(main())
