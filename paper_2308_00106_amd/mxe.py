@@ -70,6 +70,11 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         return _lib
     if not os.path.exists(path):
         raise RuntimeError(f"{path} is missing: build it with `python -m paper_2308_00106_amd.build`")
+    # torch first: its wheel carries its own HIP runtime under the same soname,
+    # so libmxe.so then binds to the copy torch already loaded and both share
+    # one runtime. Loaded the other way round, a second runtime comes in from
+    # the system and torch afterwards finds no GPU.
+    import torch  # noqa: F401
     lib = ctypes.CDLL(path)
     P, i32, i64, u32, u64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_uint64
     st = ctypes.c_int
