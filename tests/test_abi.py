@@ -119,3 +119,19 @@ def test_create_without_device_fails_cleanly(lib):
     with pytest.raises(mx.MxeError) as e:
         mx.Context(0)
     assert e.value.status in (mx.ERR_DEVICE, mx.ERR_INVALID_ARG)
+
+
+def test_library_shares_torchs_hip_runtime():
+    """Loading the library before anything imports torch must still leave one
+    HIP runtime in the process (torch's), else torch finds no GPU later."""
+    import ast
+    import subprocess
+    import sys
+    code = ("from paper_2308_00106_amd import mxe; mxe.load_library(); "
+            "print(sorted({l.split()[-1] for l in open('/proc/self/maps') if 'libamdhip64' in l}))")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300,
+                       cwd=root)
+    assert r.returncode == 0, r.stderr
+    libs = ast.literal_eval(r.stdout.strip().splitlines()[-1])
+    assert len(libs) == 1 and "torch" in libs[0], libs
