@@ -12,7 +12,16 @@ One step = the whole hot path on inputs already resident in HBM:
 entropy amortised over the 100 reuses). Kernel-only GB/s of the permuted and
 the original matrix are reported beside it, with the same byte count.
 
-python bench.py [--gpus 1] [--steps K] [--warmup W] [--reps 100] [--extras]
+The same line also carries the rest of the metric, each part measured in this
+run (bench_extras.py): `skewed` (the n = 4M lognormal-row matrix stored FP64,
+FP32 and BF16: permuted vs original product and each one's error against the
+FP64 oracle), `batch` (64 matrices in one persistent launch replayed from a
+HIP graph) and `serving` (the 32-matrix pool: closed-loop saturation rate,
+Poisson arrivals at 0.05, 0.5 and 0.8 of it, p50 / p99 latency and aggregate
+GB/s, beside the same product run alone). --no-extras skips them; --extras
+adds the heavy-row and semiring workloads.
+
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--reps 100] [--no-extras | --extras]
 """
 from __future__ import annotations
 
@@ -211,7 +220,12 @@ def main():
     ap.add_argument("--reps", type=int, default=100)
     ap.add_argument("--n", type=int, default=2_000_000)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--extras", action="store_true", help="also measure the FP32/BF16, batch and serving workloads")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the skewed, batch and serving parts of the metric")
+    ap.add_argument("--extras", action="store_true",
+                    help="also measure the heavy-row and semiring workloads")
+    ap.add_argument("--serving-requests", type=int, default=6000,
+                    help="measured requests per serving run (after a tenth as many warm-up ones)")
     ap.add_argument("--variant", type=lambda s: int(s, 0), default=None,
                     help="force the SpMV variant of the permuted matrix (default: autotuned)")
     args = ap.parse_args()
@@ -392,9 +406,16 @@ def main():
         "paper_context": "paper reports up to ~15% from randomization on AMD GPU/CPU systems "
                          "(Vega 20 / Fiji / Ellesmere, rocSPARSE FP64); context only",
     }
-    if args.extras:
+    out["spmv"]["cold_permuted_over_original"] = round(cold["original"]["median"] /
+                                                       cold["permuted"]["median"], 4)
+    if not args.no_extras:
         import bench_extras
-        out["extras"] = bench_extras.run_all(ctx, log)
+        out["skewed"] = bench_extras.skewed(ctx, log)
+        out["batch"] = bench_extras.batch(ctx, log)
+        out["serving"] = bench_extras.serving(ctx, log, warm=args.serving_requests // 10,
+                                              n_req=args.serving_requests)
+        if args.extras:
+            out["extras"] = bench_extras.run_all(ctx, log, ("heavy", "semiring"))
     if not args.no_cpu:
         log("timing the oracle on the host")
         out["cpu_baseline"], out["cpu_context"] = cpu_baseline(A0, x, seed, reps, grid)

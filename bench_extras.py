@@ -24,6 +24,7 @@ from __future__ import annotations
 
 import threading
 import time
+from concurrent.futures import ThreadPoolExecutor
 
 import numpy as np
 
@@ -33,6 +34,13 @@ import synth
 
 def _bytes(A, val_bytes, vec_bytes, k):
     return A.nnz * (val_bytes + 4) + (A.nrows + 1) * 4 + k * (A.ncols + A.nrows) * vec_bytes
+
+
+def _generate(fn, count, workers=8):
+    """fn(0), ..., fn(count - 1) on a thread pool (each is a pure function of
+    its index; numpy releases the GIL in the heavy parts)."""
+    with ThreadPoolExecutor(workers) as ex:
+        return list(ex.map(fn, range(count)))
 
 
 def _time(ctx, m, X, Y, reps, stream, flags=0):
@@ -168,11 +176,9 @@ def batch(ctx, log, count=64, replays=20):
     import torch
     stream = torch.cuda.current_stream()
     t = time.perf_counter()
-    mats, ks = [], []
-    for i in range(count):
-        A, k = synth.batch_member(i)
-        mats.append(A)
-        ks.append(k)
+    members = _generate(synth.batch_member, count)
+    mats = [A for A, _ in members]
+    ks = [k for _, k in members]
     log(f"batch: generated {count} matrices, {sum(A.nnz for A in mats)} nnz in "
         f"{time.perf_counter() - t:.1f}s")
     hs = [ctx.permute(ctx.register(A, "f32"), 1000 + i, stream=stream) for i, A in enumerate(mats)]
@@ -222,11 +228,11 @@ def batch(ctx, log, count=64, replays=20):
     return out
 
 
-def serving(ctx_unused, log, pool=32, warm=1000, n_req=20000):
+def serving(ctx_unused, log, pool=32, warm=1000, n_req=20000, low_load_requests=1000):
     import torch
     from paper_2308_00106_amd import mxe as mx
     t = time.perf_counter()
-    mats = [synth.serving_member(i) for i in range(pool)]
+    mats = _generate(synth.serving_member, pool)
     log(f"serving: generated {pool} matrices, {sum(A.nrows for A in mats)} rows, "
         f"{sum(A.nnz for A in mats)} nnz in {time.perf_counter() - t:.1f}s")
     budget = 200 * (1 << 30)
@@ -236,19 +242,39 @@ def serving(ctx_unused, log, pool=32, warm=1000, n_req=20000):
         slots = 32
         Ys = [[torch.empty((A.nrows, 8), dtype=torch.float32, device="cuda") for _ in range(slots)]
               for A in mats]
+        t = time.perf_counter()
         for h in hs:                        # tune every k class up front
             for k in (1, 2, 4, 8, 16):
                 ctx.tune(h, k)
+        log(f"serving: tuned {pool} x 5 k classes in {time.perf_counter() - t:.1f}s")
         rng = np.random.default_rng(5)
-        total = warm + n_req
-        mi = rng.integers(0, pool, size=total)
-        ki = rng.integers(1, 9, size=total)
-        nbytes = np.array([_bytes(mats[m], 4, 4, k) for m, k in zip(mi, ki)], dtype=np.float64)
+        # the same product alone, outside the loop: GPU time (events) and the
+        # host round trip (launch + synchronize), over random pool requests
+        stream = torch.cuda.current_stream()
+        alone_gpu, alone_host = [], []
+        for _ in range(200):
+            m, k = int(rng.integers(0, pool)), int(rng.integers(1, 9))
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            th = time.perf_counter()
+            e0.record(stream)
+            ctx.spmv(hs[m], Xs[m][:, :k], Ys[m][0][:, :k], stream=stream)
+            e1.record(stream)
+            e1.synchronize()
+            alone_host.append((time.perf_counter() - th) * 1e6)
+            alone_gpu.append(e0.elapsed_time(e1) * 1e3)
+        standalone = {"gpu_p50_us": round(float(np.percentile(alone_gpu, 50)), 1),
+                      "host_round_trip_p50_us": round(float(np.percentile(alone_host, 50)), 1),
+                      "requests": len(alone_gpu)}
         ctx.serve_start(streams=4, max_inflight=32, max_merge_k=16)
 
-        def run(rate, window=256):
+        def run(rate, n_meas, n_warm, window=256):
             """rate None: closed loop (as fast as possible, at most `window`
             requests outstanding); else open-loop Poisson arrivals."""
+            total = n_warm + n_meas
+            mi = rng.integers(0, pool, size=total)
+            ki = rng.integers(1, 9, size=total)
+            nbytes = np.array([_bytes(mats[m], 4, 4, k) for m, k in zip(mi, ki)], dtype=np.float64)
             tickets = [0] * total
             finished = np.zeros(total, dtype=bool)
             lat = np.zeros(total)
@@ -268,10 +294,10 @@ def serving(ctx_unused, log, pool=32, warm=1000, n_req=20000):
             wt.start()
             gaps = rng.exponential(1.0 / rate, size=total) if rate else None
             t_next = time.perf_counter()
-            t_meas = None
+            t_meas = time.perf_counter()
             n_done = 0
             for i in range(total):
-                if i == warm:
+                if i == n_warm:
                     t_meas = time.perf_counter()
                 if rate:
                     t_next += gaps[i]
@@ -293,24 +319,29 @@ def serving(ctx_unused, log, pool=32, warm=1000, n_req=20000):
             done.wait()
             t1 = time.perf_counter()
             wt.join()
-            meas = lat[warm:]
-            return {"requests": n_req, "seconds": round(t1 - t_meas, 4),
-                    "req_per_s": round(n_req / (t1 - t_meas), 1),
-                    "gbs": round(nbytes[warm:].sum() / (t1 - t_meas) / 1e9, 1),
+            meas = lat[n_warm:]
+            return {"requests": n_meas, "seconds": round(t1 - t_meas, 4),
+                    "req_per_s": round(n_meas / (t1 - t_meas), 1),
+                    "gbs": round(nbytes[n_warm:].sum() / (t1 - t_meas) / 1e9, 1),
                     "p50_us": round(float(np.percentile(meas, 50)), 1),
                     "p99_us": round(float(np.percentile(meas, 99)), 1),
                     "mean_us": round(float(meas.mean()), 1)}
 
-        closed = run(None)
+        closed = run(None, n_req, warm)
         log(f"serving closed loop: {closed}")
         rmax = closed["req_per_s"]
         out = {"pool": pool, "rows": sum(A.nrows for A in mats), "nnz": sum(A.nnz for A in mats),
-               "budget_bytes": budget, "closed_loop": closed}
+               "budget_bytes": budget, "closed_loop": closed, "standalone_product": standalone}
         for frac in (0.5, 0.8):
-            r = run(frac * rmax)
+            r = run(frac * rmax, n_req, warm)
             r["offered_req_per_s"] = round(frac * rmax, 1)
             out[f"poisson_{frac}"] = r
             log(f"serving poisson {frac}: {r}")
+        low = run(0.05 * rmax, low_load_requests, low_load_requests // 10)
+        low["offered_req_per_s"] = round(0.05 * rmax, 1)
+        low["p50_over_standalone_gpu_p50"] = round(low["p50_us"] / standalone["gpu_p50_us"], 3)
+        out["poisson_0.05"] = low
+        log(f"serving poisson 0.05: {low}")
         ctx.serve_stop()
     return out
 

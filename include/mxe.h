@@ -150,8 +150,10 @@ mxe_status mxe_matrix_info(mxe_ctx *ctx, mxe_mat m, mxe_matrix_desc *out);
 /* Releases a handle. A permuted matrix keeps its parent's memory until it is
  * released too, and a batch plan keeps its matrices' memory until the plan is
  * destroyed. Returns MXE_ERR_BUSY while serving work on it is queued or
- * running. When the last reference to a matrix's memory goes, the device
- * finishes all queued work (on any stream) before the memory is freed. */
+ * running. When the last reference to a matrix's memory goes, the call waits
+ * for the work that library calls queued on that matrix (on each stream they
+ * used, up to its last such call) before the memory is freed; it does not
+ * wait for the rest of the device. */
 mxe_status mxe_release(mxe_ctx *ctx, mxe_mat m);
 
 /* --- measure (Sections 4 and 5) --------------------------------------------- */
@@ -272,16 +274,32 @@ typedef struct mxe_item {
     uint32_t flags;             /* MXE_SPACE_PERMUTED only in batches */
 } mxe_item;
 
-/* One persistent launch computes every item: the items are dealt to one work
- * queue per XCD (largest first onto the least loaded), and workgroups pull
- * (item, row tile) work from their own XCD's queue, then from the others. */
+/* The reuse setting of Section 1: randomization is a cheap preconditioning
+ * of the product, paid once and repaid over the many products an iterative
+ * solver (or a convolution) takes with the same resident matrix; Section 7
+ * ("randomization sometimes works") makes the same point. A batch runs many
+ * such products at once: Y_i = M_i X_i for every item (Section 2's product,
+ * k_i <= 16 right-hand sides each, permuted index space only, each X_i / Y_i
+ * laid out as for mxe_spmv). One persistent launch computes every item: the
+ * items are cut into work units (slab-layout blocks or row tiles), dealt to
+ * one work queue per XCD, and workgroups pull units from their own XCD's
+ * queue, then from the others. Stream-ordered on `stream`; the call builds
+ * its work list on the host and may tune items first (as mxe_tune).
+ * MXE_ERR_UNSUPPORTED for k > 16 or MXE_SPACE_ORIGINAL items; every item is
+ * validated before any launch. */
 mxe_status mxe_spmv_batch(mxe_ctx *ctx, int32_t count, const mxe_item *items, void *stream);
 
-/* Plans a batch once (autotunes each item, builds the work list) and captures
- * the launch in a HIP graph; mxe_batch_launch replays it. Items passed to
- * launch must name the same matrices and k in the same order; their X / Y
- * pointers may change (the descriptors are rewritten in device memory before
- * the replay). items == NULL replays with the planned pointers. */
+/* Section 1's reuse, repeated: the same batch of products on resident
+ * matrices, again and again. mxe_batch_create plans a batch once (autotunes
+ * each item, builds the work list) and captures the launch in a HIP graph
+ * (synchronizes); mxe_batch_launch replays it on `stream` (stream-ordered).
+ * Items passed to launch must name the same matrices and k in the same
+ * order; their X / Y pointers may change (the descriptor table is rewritten
+ * on the device, ordered after the previous replay). items == NULL replays
+ * with the current pointers. Replays of one plan never overlap: each waits
+ * on the device for the previous one, whatever stream that ran on. The plan
+ * keeps its matrices alive until mxe_batch_destroy, which waits for the last
+ * replay. */
 mxe_status mxe_batch_create(mxe_ctx *ctx, int32_t count, const mxe_item *items, mxe_plan *out);
 mxe_status mxe_batch_launch(mxe_ctx *ctx, mxe_plan plan, const mxe_item *items, void *stream);
 mxe_status mxe_batch_destroy(mxe_ctx *ctx, mxe_plan plan);
@@ -299,12 +317,21 @@ typedef struct mxe_serve_config {
  * free; queued requests on the same matrix are merged into one multi-RHS
  * product up to max_merge_k; work overlaps on `streams` device streams. */
 mxe_status mxe_serve_start(mxe_ctx *ctx, const mxe_serve_config *cfg);
-/* Queues a request (X, Y stay owned by the caller and must stay alive until
- * mxe_wait returns MXE_OK for it). Thread-safe. */
+/* Serving is Section 1's reuse as a service: matrices are permuted once and
+ * stay resident; each request is one product Y = M X (Section 2; Eq. 1 when
+ * flags is MXE_SPACE_ORIGINAL), k >= 1 right-hand sides laid out as for
+ * mxe_spmv. Queues a request and returns its ticket at once (X, Y stay owned
+ * by the caller and must stay alive until mxe_wait returns for it; the
+ * matrix's own creation, e.g. the stream given to mxe_permute, must be
+ * complete). MXE_ERR_INVALID_ARG for a bad request or no running loop,
+ * MXE_ERR_NOT_FOUND for an unknown matrix. Thread-safe. */
 mxe_status mxe_submit(mxe_ctx *ctx, const mxe_item *req, mxe_ticket *out);
-/* Blocks until the request is done (timeout_us < 0: forever). On MXE_OK the
- * ticket is retired and *latency_us (may be NULL) holds submit-to-completion
- * time. MXE_ERR_TIMEOUT leaves the ticket live. Thread-safe. */
+/* The completion side of a Section 1 reuse request (see mxe_submit). Blocks
+ * until the request is done (timeout_us < 0: forever). On return other than
+ * MXE_ERR_TIMEOUT the ticket is retired; on MXE_OK *latency_us (may be NULL)
+ * holds submit-to-completion time, else the status is the request's own
+ * failure (MXE_ERR_BUDGET for a request that can never fit the budget).
+ * MXE_ERR_TIMEOUT leaves the ticket live. Thread-safe. */
 mxe_status mxe_wait(mxe_ctx *ctx, mxe_ticket t, int64_t timeout_us, double *latency_us);
 /* Drains queued and running requests, then stops the loop. */
 mxe_status mxe_serve_stop(mxe_ctx *ctx);

@@ -21,6 +21,9 @@ Parity status per function (what pins it is in tests/test_oracle.py):
   gradient_permutation, permute_gradient
                                     pinned (hand-built step profile, ties, edges, scipy slicing)
   round_f32, round_bf16             pinned (IEEE halfway cases, torch for FP32-exact inputs)
+  bf16_to_f64                       pinned (hand-decoded bit patterns, torch on all 65536)
+  stored_values                     pinned (numpy float32 rounding, golden BF16 cases decoded
+                                    by Python's binary32 unpacking, torch on FP32-exact inputs)
   normalized_error                  pinned (hand cases)
 """
 from __future__ import annotations

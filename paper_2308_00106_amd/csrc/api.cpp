@@ -102,14 +102,18 @@ mxe_status reserve(mxe_ctx *ctx, uint64_t bytes) {
     }
 }
 
+// When the last reference goes, the work each stream queued on the matrix
+// (its last recorded use) finishes before the memory returns to the pool;
+// other streams and unrelated work are not waited for.
 std::shared_ptr<Matrix> make_matrix(mxe_ctx *ctx) {
     int dev = ctx->device;
     return std::shared_ptr<Matrix>(new Matrix(), [ctx, dev](Matrix *m) {
         DeviceGuard g(dev);
-        (void)hipDeviceSynchronize();
+        for (const Matrix::Use &u : m->uses) {
+            (void)hipEventSynchronize(u.ev);
+            (void)hipEventDestroy(u.ev);
+        }
         for (void *p : m->allocs) (void)hipFreeAsync(p, nullptr);
-        if (m->merge_ws) (void)hipFreeAsync(m->merge_ws, nullptr);
-        (void)hipStreamSynchronize(nullptr);
         ctx->used -= m->bytes;
         delete m;
     });
@@ -118,6 +122,19 @@ std::shared_ptr<Matrix> make_matrix(mxe_ctx *ctx) {
 int64_t root_of(const Matrix &m) { return m.parent ? m.parent->id : m.id; }
 
 }  // namespace
+
+mxe_status note_use(Matrix &A, hipStream_t s) {
+    for (Matrix::Use &u : A.uses)
+        if (u.s == s) {
+            MXE_HIP(hipEventRecord(u.ev, s));
+            return MXE_OK;
+        }
+    Matrix::Use u{s, nullptr};
+    MXE_HIP(hipEventCreateWithFlags(&u.ev, hipEventDisableTiming));
+    A.uses.push_back(u);
+    MXE_HIP(hipEventRecord(u.ev, s));
+    return MXE_OK;
+}
 
 std::shared_ptr<Matrix> find_matrix(mxe_ctx *ctx, mxe_mat h) {
     auto it = ctx->mats.find(h);
@@ -153,31 +170,41 @@ static mxe_status ensure_bins(mxe_ctx *, Matrix &A, hipStream_t s) {
     return MXE_OK;
 }
 
-static mxe_status ensure_merge_ws(Matrix &A, hipStream_t s) {
-    if (A.merge_ws) return MXE_OK;
-    hipError_t e = hipMallocAsync(&A.merge_ws, merge_ws_bytes(A.nrows, A.nnz), s);
-    if (e != hipSuccess) {
-        A.merge_ws = nullptr;
-        return hip_fail(e, "hipMallocAsync(merge workspace)");
-    }
-    return MXE_OK;
-}
+// Structures built once per matrix on the calling stream are finished
+// (the stream synchronized) before any launch uses them, so a launch on
+// another stream never reads one half built; afterwards they are read only.
 
-// COO row index and carry workspace (built once per matrix)
-static mxe_status ensure_coo(mxe_ctx *ctx, Matrix &A, hipStream_t s) {
-    if (A.coo_row) return MXE_OK;
-    const uint64_t bytes = 4ull * (uint64_t)A.nnz + coo_ws_bytes(A.nnz);
+// merge-path slice starts (built once per matrix)
+static mxe_status ensure_merge(mxe_ctx *ctx, Matrix &A, hipStream_t s) {
+    if (A.merge_coords) return MXE_OK;
+    const uint64_t bytes = merge_coords_bytes(A.nrows, A.nnz);
     mxe_status st;
     if ((st = reserve(ctx, bytes))) return st;
     A.bytes += bytes;
-    void *r, *w;
-    if ((st = dev_alloc(A, &r, 4 * (size_t)A.nnz, s))) return st;
-    if ((st = dev_alloc(A, &w, coo_ws_bytes(A.nnz), s))) return st;
-    MXE_HIP(launch_coo_rows(A.nrows, A.rp, (int32_t *)r, s));
-    A.coo_row = (int32_t *)r;
-    A.coo_ws = w;
+    void *p;
+    if ((st = dev_alloc(A, &p, bytes, s))) return st;
+    MXE_HIP(launch_merge_coords(A.nrows, A.nnz, A.rp, p, s));
+    MXE_HIP(hipStreamSynchronize(s));
+    A.merge_coords = p;
     return MXE_OK;
 }
+
+// COO row index per entry (built once per matrix)
+static mxe_status ensure_coo(mxe_ctx *ctx, Matrix &A, hipStream_t s) {
+    if (A.coo_row) return MXE_OK;
+    const uint64_t bytes = 4ull * (uint64_t)A.nnz;
+    mxe_status st;
+    if ((st = reserve(ctx, bytes))) return st;
+    A.bytes += bytes;
+    void *r;
+    if ((st = dev_alloc(A, &r, 4 * (size_t)A.nnz, s))) return st;
+    MXE_HIP(launch_coo_rows(A.nrows, A.rp, (int32_t *)r, s));
+    MXE_HIP(hipStreamSynchronize(s));
+    A.coo_row = (int32_t *)r;
+    return MXE_OK;
+}
+
+static int kclass_of(int32_t k) { return k <= 1 ? 1 : k <= 2 ? 2 : k <= 4 ? 4 : k <= 8 ? 8 : 16; }
 
 static SpmvArgs make_args(Matrix &A, int32_t k, const void *X, int64_t ldx, void *Y, int64_t ldy) {
     SpmvArgs a{};
@@ -195,13 +222,18 @@ static SpmvArgs make_args(Matrix &A, int32_t k, const void *X, int64_t ldx, void
     a.ldy = ldy;
     a.bin_list = A.bin_list;
     a.bin_off_host = A.bin_off;
-    a.merge_ws = A.merge_ws;
+    a.merge_coords = A.merge_coords;
     a.coo_row = A.coo_row;
-    a.coo_ws = A.coo_ws;
     return a;
 }
 
-static int kclass_of(int32_t k) { return k <= 1 ? 1 : k <= 2 ? 2 : k <= 4 ? 4 : k <= 8 ? 8 : 16; }
+// bytes of the launch's own carry workspace: MERGE and COO, else 0
+static size_t carry_bytes(const Matrix &A, int variant, int32_t k) {
+    const int family = variant & 0xf00;
+    if (family == MXE_VAR_MERGE) return merge_carry_bytes(A.nrows, A.nnz);
+    if (family == MXE_VAR_COO) return coo_ws_bytes(A.nnz, kclass_of(k), elem_bytes_of(A.storage));
+    return 0;
+}
 
 static TuneKey tune_key(const Matrix &A, int32_t k) {
     return TuneKey{A.nrows, A.ncols, A.nnz, (int32_t)A.storage, kclass_of(k),
@@ -249,6 +281,7 @@ static mxe_status ensure_slab(mxe_ctx *ctx, Matrix &A, int kclass, int units, in
     Scratch ws;
     if ((st = ws.alloc(slab_build_ws_bytes(sl.g), s))) return st;
     MXE_HIP(launch_slab_build(sl.g, A.rp, A.col, A.val, vb, sl.off, sl.idx, sl.val, ws.p, s));
+    MXE_HIP(hipStreamSynchronize(s));
     *out = &(A.slabs[key] = sl);
     return MXE_OK;
 }
@@ -270,7 +303,7 @@ static mxe_status prepare_args(mxe_ctx *ctx, Matrix &A, int variant, int32_t k, 
     const int family = variant & 0xf00;
     mxe_status st;
     if (family == MXE_VAR_BINNED && (st = ensure_bins(ctx, A, s))) return st;
-    if (family == MXE_VAR_MERGE && (st = ensure_merge_ws(A, s))) return st;
+    if (family == MXE_VAR_MERGE && (st = ensure_merge(ctx, A, s))) return st;
     if (family == MXE_VAR_COO && (st = ensure_coo(ctx, A, s))) return st;
     *a = make_args(A, k, X, ldx, Y, ldy);
     if (family == MXE_VAR_SLAB) {
@@ -325,6 +358,11 @@ static mxe_status tune(mxe_ctx *ctx, Matrix &A, int32_t k, hipStream_t s, TuneRe
         SpmvArgs a;
         mxe_status st2 = prepare_args(ctx, A, v, kc, xs.p, kc, ys.p, kc, s, &a);
         if (st2) return st2;
+        Scratch cw;
+        if (const size_t cb = carry_bytes(A, v, kc)) {
+            if ((st2 = cw.alloc(cb, s))) return st2;
+            a.carry_ws = cw.p;
+        }
         hipError_t e = launch_spmv(a, v, s);
         if (e == hipSuccess) e = hipEventRecord(e0, s);
         for (int i = 0; i < reps && e == hipSuccess; ++i) e = launch_spmv(a, v, s);
@@ -429,6 +467,11 @@ static mxe_status spmv_core(mxe_ctx *ctx, Matrix &A, int32_t k, const void *X, i
         if ((st = prepare_args(ctx, A, r.variant, kc, (const char *)X + (size_t)c0 * eb, ldx,
                                (char *)Y + (size_t)c0 * eb, ldy, s, &a)))
             return st;
+        Scratch cw;                             // this launch's carries (MERGE, COO)
+        if (const size_t cb = carry_bytes(A, r.variant, kc)) {
+            if ((st = cw.alloc(cb, s))) return st;
+            a.carry_ws = cw.p;
+        }
         MXE_HIP(launch_spmv(a, r.variant, s));
     }
     return MXE_OK;
@@ -436,7 +479,10 @@ static mxe_status spmv_core(mxe_ctx *ctx, Matrix &A, int32_t k, const void *X, i
 
 mxe_status spmv_internal(mxe_ctx *ctx, Matrix &A, int32_t k, const void *X, int64_t ldx, void *Y,
                          int64_t ldy, uint32_t flags, hipStream_t s) {
-    if (!(flags & MXE_SPACE_ORIGINAL) || !A.rperm) return spmv_core(ctx, A, k, X, ldx, Y, ldy, s);
+    if (!(flags & MXE_SPACE_ORIGINAL) || !A.rperm) {
+        mxe_status st = spmv_core(ctx, A, k, X, ldx, Y, ldy, s);
+        return st ? st : note_use(A, s);
+    }
     // Eq. 1: y = P_r^-1 (B (P_c^-1 x))
     const int eb = elem_bytes_of(A.storage);
     Scratch xp, yp;
@@ -446,7 +492,7 @@ mxe_status spmv_internal(mxe_ctx *ctx, Matrix &A, int32_t k, const void *X, int6
     MXE_HIP(launch_gather_rows(A.ncols, k, A.cperm, X, ldx, xp.p, k, eb, s));
     if ((st = spmv_core(ctx, A, k, xp.p, k, yp.p, k, s))) return st;
     MXE_HIP(launch_scatter_rows(A.nrows, k, A.rperm, yp.p, k, Y, ldy, eb, s));
-    return MXE_OK;
+    return note_use(A, s);
 }
 
 }  // namespace mxe
@@ -691,6 +737,7 @@ mxe_status mxe_permute(mxe_ctx *ctx, mxe_mat a, uint64_t seed, uint32_t mode, vo
     MXE_HIP(launch_gather_relabel_sort(M, A->rp, A->col, A->val, vb, B->rinv,
                                        (mode & MXE_COLS) ? B->cinv : nullptr, B->rp, B->col,
                                        B->val, s));
+    if ((st = note_use(*A, s)) || (st = note_use(*B, s))) return st;
     B->id = ctx->next_id++;
     ctx->mats[B->id] = B;
     *out_b = B->id;
@@ -919,8 +966,10 @@ mxe_status mxe_spmv_semiring(mxe_ctx *ctx, mxe_mat m, int32_t semiring, int32_t 
     mxe_status st = check_dense(*A, k, X, ldx, Y, ldy);
     if (st) return st;
     hipStream_t s = (hipStream_t)stream;
-    if (!(flags & MXE_SPACE_ORIGINAL) || !A->rperm)
-        return semiring_core(ctx, *A, semiring, k, X, ldx, Y, ldy, s);
+    if (!(flags & MXE_SPACE_ORIGINAL) || !A->rperm) {
+        st = semiring_core(ctx, *A, semiring, k, X, ldx, Y, ldy, s);
+        return st ? st : note_use(*A, s);
+    }
     const int eb = elem_bytes_of(A->storage);
     Scratch xp, yp;
     if ((st = xp.alloc((size_t)eb * std::max(A->ncols, 1) * k, s))) return st;
@@ -928,7 +977,7 @@ mxe_status mxe_spmv_semiring(mxe_ctx *ctx, mxe_mat m, int32_t semiring, int32_t 
     MXE_HIP(launch_gather_rows(A->ncols, k, A->cperm, X, ldx, xp.p, k, eb, s));
     if ((st = semiring_core(ctx, *A, semiring, k, xp.p, k, yp.p, k, s))) return st;
     MXE_HIP(launch_scatter_rows(A->nrows, k, A->rperm, yp.p, k, Y, ldy, eb, s));
-    return MXE_OK;
+    return note_use(*A, s);
 }
 
 mxe_status mxe_gather_x(mxe_ctx *ctx, mxe_mat b, int32_t k, const void *X, int64_t ldx, void *Xp,
@@ -947,7 +996,7 @@ mxe_status mxe_gather_x(mxe_ctx *ctx, mxe_mat b, int32_t k, const void *X, int64
         return MXE_OK;
     }
     MXE_HIP(launch_gather_rows(B->ncols, k, B->cperm, X, ldx, Xp, ldxp, eb, s));
-    return MXE_OK;
+    return note_use(*B, s);
 }
 
 mxe_status mxe_scatter_y(mxe_ctx *ctx, mxe_mat b, int32_t k, const void *Yp, int64_t ldyp, void *Y,
@@ -966,7 +1015,7 @@ mxe_status mxe_scatter_y(mxe_ctx *ctx, mxe_mat b, int32_t k, const void *Yp, int
         return MXE_OK;
     }
     MXE_HIP(launch_scatter_rows(B->nrows, k, B->rperm, Yp, ldyp, Y, ldy, eb, s));
-    return MXE_OK;
+    return note_use(*B, s);
 }
 
 mxe_status mxe_tune(mxe_ctx *ctx, mxe_mat m, int32_t k, void *stream, int32_t *variant) {
@@ -1187,6 +1236,8 @@ mxe_status mxe_spmv_batch(mxe_ctx *ctx, int32_t count, const mxe_item *items, vo
     MXE_HIP(launch_batch_reset(counters, s));
     MXE_HIP(launch_spmv_batch((const BatchDesc *)dd.p, counters + kBatchQueues, qs, counters, grid,
                               lds, vt, s));
+    for (int32_t i = 0; i < count; ++i)
+        if ((st = note_use(*find_matrix(ctx, items[i].mat), s))) return st;
     return MXE_OK;
 }
 
@@ -1203,6 +1254,10 @@ mxe_status mxe_batch_create(mxe_ctx *ctx, int32_t count, const mxe_item *items, 
     if (plan->grid < 1) return fail(MXE_ERR_DEVICE, "batch kernel occupancy query failed");
     plan->items.assign(items, items + count);
     for (int32_t i = 0; i < count; ++i) plan->mats.push_back(find_matrix(ctx, items[i].mat));
+    MXE_HIP(hipEventCreateWithFlags(&plan->done, hipEventDisableTiming));
+    MXE_HIP(hipEventCreateWithFlags(&plan->staged, hipEventDisableTiming));
+    MXE_HIP(hipHostMalloc((void **)&plan->staging, sizeof(BatchDesc) * plan->descs.size(),
+                          hipHostMallocDefault));
     MXE_HIP(hipMalloc(&plan->descs_dev, sizeof(BatchDesc) * plan->descs.size()));
     MXE_HIP(hipMalloc(&plan->counters, sizeof(int32_t) * (kBatchQueues + plan->qent.size())));
     MXE_HIP(hipMemcpy(plan->descs_dev, plan->descs.data(), sizeof(BatchDesc) * plan->descs.size(),
@@ -1258,13 +1313,20 @@ mxe_status mxe_batch_launch(mxe_ctx *ctx, mxe_plan h, const mxe_item *items, voi
             p.items[i] = items[i];
         }
         if (changed) {
-            // the previous replay may still read the table: order the rewrite after it
-            MXE_HIP(hipStreamSynchronize(s));
-            MXE_HIP(hipMemcpy(p.descs_dev, p.descs.data(), sizeof(BatchDesc) * p.descs.size(),
-                              hipMemcpyHostToDevice));
+            // the pinned staging copy is free once the previous rewrite ran;
+            // the rewrite itself waits on the device for the previous replay
+            MXE_HIP(hipEventSynchronize(p.staged));
+            std::memcpy(p.staging, p.descs.data(), sizeof(BatchDesc) * p.descs.size());
+            MXE_HIP(hipStreamWaitEvent(s, p.done, 0));
+            MXE_HIP(hipMemcpyAsync(p.descs_dev, p.staging, sizeof(BatchDesc) * p.descs.size(),
+                                   hipMemcpyHostToDevice, s));
+            MXE_HIP(hipEventRecord(p.staged, s));
         }
     }
+    // the previous replay (on any stream) shares the work counters: finish it first
+    MXE_HIP(hipStreamWaitEvent(s, p.done, 0));
     MXE_HIP(hipGraphLaunch(p.exec, s));
+    MXE_HIP(hipEventRecord(p.done, s));
     return MXE_OK;
 }
 
@@ -1274,8 +1336,7 @@ mxe_status mxe_batch_destroy(mxe_ctx *ctx, mxe_plan h) {
     DeviceGuard g(ctx->device);
     auto it = ctx->plans.find(h);
     if (it == ctx->plans.end()) return fail(MXE_ERR_NOT_FOUND, "unknown plan handle");
-    (void)hipDeviceSynchronize();                   // replays finish before ~Plan frees
-    ctx->plans.erase(it);
+    ctx->plans.erase(it);                           // ~Plan waits for the last replay
     return MXE_OK;
 }
 

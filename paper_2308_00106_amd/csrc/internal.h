@@ -140,22 +140,29 @@ struct SpmvArgs {
     // binned variant
     const int32_t *bin_list;
     const int32_t *bin_off_host;   // kNumBins + 1 host ints
-    // merge variant workspace (merge_ws_bytes)
-    void *merge_ws;
+    // merge variant: the matrix's slice starts (merge_coords_bytes, built once
+    // by launch_merge_coords, read only)
+    const void *merge_coords;
+    // MERGE / COO: this launch's own carry workspace (merge_carry_bytes /
+    // coo_ws_bytes); never shared between launches that may overlap
+    void *carry_ws;
     // slab variant layout (null when not built)
     const SlabGeom *slab;
     const int32_t *slab_off;
     const uint32_t *slab_idx;
     const void *slab_val;
-    // COO variant: row index per entry and its carry workspace (coo_ws_bytes)
+    // COO variant: row index per entry (built once, read only)
     const int32_t *coo_row;
-    void *coo_ws;
 };
 
-size_t merge_ws_bytes(int32_t nrows, int64_t nnz);
+size_t merge_coords_bytes(int32_t nrows, int64_t nnz);
+size_t merge_carry_bytes(int32_t nrows, int64_t nnz);
+hipError_t launch_merge_coords(int32_t nrows, int64_t nnz, const int32_t *rp, void *coords,
+                               hipStream_t s);
 // Y = M X over MXE_SR_MIN_PLUS or MXE_SR_OR_AND (mxe.h), k <= 16.
 hipError_t launch_spmv_semiring(const SpmvArgs &a, int semiring, hipStream_t s);
-size_t coo_ws_bytes(int64_t nnz);                 // enough for k <= 16
+// one COO launch's carries for k class kclass and elem_bytes-wide sums
+size_t coo_ws_bytes(int64_t nnz, int kclass, int elem_bytes);
 hipError_t launch_coo_rows(int32_t nrows, const int32_t *rp, int32_t *row, hipStream_t s);
 // variant: MXE_VARIANT(family, lanes) as in mxe.h
 hipError_t launch_spmv(const SpmvArgs &a, int variant, hipStream_t s);

@@ -463,15 +463,15 @@ __global__ __launch_bounds__(kBlock) void k_coo_fixup(int64_t ntiles, const int3
 
 template <typename V, typename T, int KM>
 hipError_t coo_launch(const SpmvArgs &a, hipStream_t s) {
-    if (!a.coo_row || !a.coo_ws) return hipErrorInvalidValue;
+    if (!a.coo_row || !a.carry_ws) return hipErrorInvalidValue;
     if (a.nnz == 0) {
         hipLaunchKernelGGL((k_zero_rows<T, KM>), dim3((unsigned)std::min<int64_t>(cdiv((int64_t)a.nrows * a.k, kBlock), 4096)),
                            dim3(kBlock), 0, s, a.nrows, a.k, (T *)a.Y, a.ldy);
         return hipGetLastError();
     }
     const int64_t ntiles = cdiv(a.nnz, kCooTile);
-    int32_t *crow = (int32_t *)a.coo_ws;
-    T *cval = (T *)((char *)a.coo_ws + ((sizeof(int32_t) * 2 * ntiles + 255) & ~size_t(255)));
+    int32_t *crow = (int32_t *)a.carry_ws;
+    T *cval = (T *)((char *)a.carry_ws + ((sizeof(int32_t) * 2 * ntiles + 255) & ~size_t(255)));
     hipLaunchKernelGGL((k_spmv_coo<V, T, KM>), dim3((unsigned)cdiv(ntiles, kBlock / kWave)),
                        dim3(kBlock), 0, s, a.nrows, a.nnz, a.coo_row, a.col, (const V *)a.val, a.k,
                        (const T *)a.X, a.ldx, (T *)a.Y, a.ldy, crow, cval);
@@ -576,14 +576,19 @@ hipError_t group_by_lanes(const SpmvArgs &a, int lanes, const int32_t *rows, int
     return hipGetLastError();
 }
 
+inline int32_t merge_tiles(int32_t nrows, int64_t nnz) {
+    return (int32_t)std::max<int64_t>(1, cdiv((int64_t)nrows + nnz, kMergeTile));
+}
+
+// coords: the matrix's slice starts (launch_merge_coords, read only here);
+// the carries live in the launch's own workspace, so launches of one matrix
+// on different streams never share them
 template <typename V, typename T, int KM>
 hipError_t merge_launch(const SpmvArgs &a, hipStream_t s) {
-    const int64_t total = (int64_t)a.nrows + a.nnz;
-    const int32_t ntiles = (int32_t)std::max<int64_t>(1, cdiv(total, kMergeTile));
-    Coord *coords = (Coord *)a.merge_ws;
-    Carry *carry = (Carry *)((char *)a.merge_ws + ((sizeof(Coord) * (ntiles + 1) + 255) & ~255ull));
-    hipLaunchKernelGGL(k_merge_coords, dim3(cdiv(ntiles + 1, kBlock)), dim3(kBlock), 0, s, a.nrows,
-                       a.nnz, a.rp, ntiles, coords);
+    if (!a.merge_coords || !a.carry_ws) return hipErrorInvalidValue;
+    const int32_t ntiles = merge_tiles(a.nrows, a.nnz);
+    const Coord *coords = (const Coord *)a.merge_coords;
+    Carry *carry = (Carry *)a.carry_ws;
     hipLaunchKernelGGL((k_spmv_merge<V, T, KM>), dim3(ntiles), dim3(kBlock), 0, s, a.nrows, a.nnz,
                        a.rp, a.col, (const V *)a.val, a.k, (const T *)a.X, a.ldx, (T *)a.Y, a.ldy,
                        (const Coord *)coords, carry);
@@ -632,9 +637,20 @@ hipError_t spmv_t(const SpmvArgs &a, int variant, hipStream_t s) {
 
 }  // namespace
 
-size_t merge_ws_bytes(int32_t nrows, int64_t nnz) {
-    const int64_t ntiles = std::max<int64_t>(1, cdiv((int64_t)nrows + nnz, kMergeTile));
-    return ((sizeof(Coord) * (ntiles + 1) + 255) & ~255ull) + sizeof(Carry) * ntiles + 256;
+size_t merge_coords_bytes(int32_t nrows, int64_t nnz) {
+    return sizeof(Coord) * ((size_t)merge_tiles(nrows, nnz) + 1);
+}
+
+size_t merge_carry_bytes(int32_t nrows, int64_t nnz) {
+    return sizeof(Carry) * (size_t)merge_tiles(nrows, nnz);
+}
+
+hipError_t launch_merge_coords(int32_t nrows, int64_t nnz, const int32_t *rp, void *coords,
+                               hipStream_t s) {
+    const int32_t ntiles = merge_tiles(nrows, nnz);
+    hipLaunchKernelGGL(k_merge_coords, dim3(cdiv(ntiles + 1, kBlock)), dim3(kBlock), 0, s, nrows,
+                       nnz, rp, ntiles, (Coord *)coords);
+    return hipGetLastError();
 }
 
 hipError_t launch_spmv_semiring(const SpmvArgs &a, int semiring, hipStream_t s) {
@@ -647,9 +663,10 @@ hipError_t launch_spmv_semiring(const SpmvArgs &a, int semiring, hipStream_t s) 
     }
 }
 
-size_t coo_ws_bytes(int64_t nnz) {
+size_t coo_ws_bytes(int64_t nnz, int kclass, int elem_bytes) {
     const int64_t ntiles = std::max<int64_t>(1, cdiv(nnz, kCooTile));
-    return ((sizeof(int32_t) * 2 * ntiles + 255) & ~size_t(255)) + sizeof(double) * 2 * ntiles * 16;
+    return ((sizeof(int32_t) * 2 * ntiles + 255) & ~size_t(255)) +
+           (size_t)elem_bytes * 2 * ntiles * kclass;
 }
 
 hipError_t launch_coo_rows(int32_t nrows, const int32_t *rp, int32_t *row, hipStream_t s) {

@@ -49,9 +49,8 @@ struct Matrix {
     int32_t *bin_off_dev = nullptr;
     int32_t bin_off[kNumBins + 1] = {};
     bool bins_ready = false;
-    void *merge_ws = nullptr;
+    void *merge_coords = nullptr;       // merge-path slice starts (an entry of allocs)
     int32_t *coo_row = nullptr;         // COO row index per entry (an entry of allocs)
-    void *coo_ws = nullptr;             // COO tile carries (an entry of allocs)
     struct Slab {
         SlabGeom g;
         int32_t *off = nullptr;
@@ -62,6 +61,13 @@ struct Matrix {
     std::map<std::tuple<int, int, int>, Slab> slabs;
     std::atomic<int> busy{0};           // serving requests queued or running
     std::vector<void *> allocs;         // device allocations to free
+    // per stream, an event recorded after the last work queued there on this
+    // matrix: freeing waits for these, never for the whole device
+    struct Use {
+        hipStream_t s;
+        hipEvent_t ev;
+    };
+    std::vector<Use> uses;
 };
 
 struct TuneKey {
@@ -92,19 +98,30 @@ struct Plan {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     hipStream_t capture_stream = nullptr;
+    // replays of one plan run one after another, whatever their streams:
+    // each waits for `done`, recorded after the previous replay (and before
+    // that, the descriptor table's rewrite from the pinned `staging` copy,
+    // whose own completion `staged` marks)
+    hipEvent_t done = nullptr, staged = nullptr;
+    BatchDesc *staging = nullptr;
 
     Plan() = default;
     Plan(const Plan &) = delete;
     Plan &operator=(const Plan &) = delete;
-    // Frees what the plan holds, whatever step of its creation it reached.
-    // The caller has the plan's device current and its replays finished; the
+    // Frees what the plan holds, whatever step of its creation it reached,
+    // after its last replay. The caller has the plan's device current; the
     // matrix references go after the graph (members are destroyed after the body).
     ~Plan() {
+        if (done) (void)hipEventSynchronize(done);
+        if (staged) (void)hipEventSynchronize(staged);
         if (exec) (void)hipGraphExecDestroy(exec);
         if (graph) (void)hipGraphDestroy(graph);
         if (capture_stream) (void)hipStreamDestroy(capture_stream);
         if (descs_dev) (void)hipFree(descs_dev);
         if (counters) (void)hipFree(counters);
+        if (staging) (void)hipHostFree(staging);
+        if (done) (void)hipEventDestroy(done);
+        if (staged) (void)hipEventDestroy(staged);
     }
 };
 
@@ -129,6 +146,8 @@ namespace mxe {
 
 // internal helpers implemented in api.cpp, used by serve.cpp
 std::shared_ptr<Matrix> find_matrix(mxe_ctx *ctx, mxe_mat m);
+// Records that work on A was queued on s (see Matrix::uses).
+mxe_status note_use(Matrix &A, hipStream_t s);
 mxe_status spmv_internal(mxe_ctx *ctx, Matrix &A, int32_t k, const void *X, int64_t ldx, void *Y,
                          int64_t ldy, uint32_t flags, hipStream_t s);
 mxe_status ensure_variant(mxe_ctx *ctx, Matrix &A, int32_t k, hipStream_t s, TuneResult *out);

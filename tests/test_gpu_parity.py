@@ -83,7 +83,13 @@ CSR_CASES = [
     ("clustered_n4096", lambda: synth.clustered_n4096(1)),
     ("ragged", lambda: synth.random_csr(4096 * 3 + 17, 9001, 0.002, 2, empty_rows=0.1)),
     ("wide", lambda: synth.random_csr(333, 20000, 0.01, 3)),
-    ("long_rows", lambda: synth.random_csr(700, 3000, 0.15, 4)),     # rows > 256: global path
+    # ~450 entries per row: groups of rows exceed the 1024-entry LDS stage, so
+    # rows move one at a time, each staged in LDS
+    ("long_rows", lambda: synth.random_csr(700, 3000, 0.15, 4)),
+    # rows of 1025-8000 entries (columns 1M, so no row is dense): longer than
+    # the stage, each entry is ranked against cinv in global memory
+    ("rows_over_1024", lambda: synth.block_clustered(
+        48, np.random.default_rng(6).integers(1025, 8001, size=48), 4096, 0.1, 6, ncols=1_000_000)),
     ("empty", lambda: synth.random_csr(50, 60, 0.0, 5)),
     ("skewed", lambda: synth.skewed_n4m(1, n=60_000)),
 ]

@@ -413,6 +413,65 @@ def test_bf16_matches_torch_on_fp32_exact_inputs():
     assert np.array_equal(oracle.round_bf16(v32.astype(np.float64)), ref)
 
 
+def _golden_bf16_decode():
+    cases = []
+    with open(os.path.join(GOLDEN, "bf16_decode_cases.txt")) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            bits, rest = line.split(None, 1)
+            expr = rest.split("  ")[0].strip()
+            val = float(expr) if expr in ("inf", "-inf") else float(eval(expr, {"__builtins__": {}}))
+            cases.append((int(bits, 16), val))
+    return cases
+
+
+def test_bf16_to_f64_hand_decoded_patterns():
+    """The oracle's BF16 decode gives the exact values worked out by hand from
+    the bit layout (sign, exponent bias, subnormals, infinities)."""
+    cases = _golden_bf16_decode()
+    assert len(cases) >= 12
+    got = oracle.bf16_to_f64(np.array([b for b, _ in cases], np.uint16))
+    for (bits, want), g in zip(cases, got):
+        assert g == want and math.copysign(1.0, g) == math.copysign(1.0, want), (hex(bits), g, want)
+    assert np.isnan(oracle.bf16_to_f64(np.array([0x7FC0, 0xFFC1], np.uint16))).all()
+
+
+def test_bf16_to_f64_matches_torch_on_every_pattern():
+    """All 65536 BF16 patterns decode to torch's bfloat16 -> float64 value."""
+    torch = pytest.importorskip("torch")
+    bits = np.arange(1 << 16, dtype=np.uint32).astype(np.uint16)
+    ref = torch.from_numpy(bits.view(np.int16)).view(torch.bfloat16).to(torch.float64).numpy()
+    with np.errstate(invalid="ignore"):              # signalling NaN patterns
+        got = oracle.bf16_to_f64(bits)
+    nan = np.isnan(ref)
+    assert np.array_equal(np.isnan(got), nan)
+    assert np.array_equal(got[~nan].view(np.uint64), ref[~nan].view(np.uint64))
+
+
+def test_stored_values_per_storage():
+    """What the GPU stores, as FP64: the value itself (FP64), numpy's IEEE
+    rounding to float32 (FP32), and for BF16 the golden rounding cases decoded
+    by Python's own binary32 unpacking, plus torch's rounding on FP32-exact
+    inputs."""
+    import struct
+    rng = np.random.default_rng(4)
+    v = np.concatenate([rng.uniform(-1, 1, 5000), rng.standard_normal(5000) * 1e20])
+    assert np.array_equal(oracle.stored_values(v, "f64").view(np.uint64), v.view(np.uint64))
+    f32 = oracle.stored_values(v, "f32")
+    assert np.array_equal(f32.view(np.uint64), v.astype(np.float32).astype(np.float64).view(np.uint64))
+    for x, bits in _golden_bf16():
+        want = struct.unpack(">f", struct.pack(">I", bits << 16))[0]
+        got = float(oracle.stored_values(np.array([x]), "bf16")[0])
+        assert got == want and math.copysign(1.0, got) == math.copysign(1.0, want), (x, hex(bits))
+    torch = pytest.importorskip("torch")
+    v32 = v.astype(np.float32)
+    ref = torch.from_numpy(v32).to(torch.bfloat16).to(torch.float64).numpy()
+    assert np.array_equal(oracle.stored_values(v32.astype(np.float64), "bf16"), ref)
+    with pytest.raises(ValueError):
+        oracle.stored_values(v, "f16")
+
+
 def test_f32_rounding_matches_numpy_and_nan_bf16():
     v = np.random.default_rng(2).uniform(-1, 1, 10000)
     assert np.array_equal(oracle.round_f32(v), v.astype(np.float32))
