@@ -61,7 +61,7 @@ def kernel_source_hash(variant_hex: str = "0x300") -> str:
         return " ".join(text.split()).encode()
 
     csrc = os.path.join(ROOT, "paper_2308_00106_amd", "csrc")
-    slab = (int(variant_hex, 16) & 0xf00) == 0x300
+    slab = (int(variant_hex, 16) & 0xf00) in (0x300, 0x600)     # SLAB, WINDOW
     h = hashlib.sha256()
     files = ("kernels_slab.hip", "slab_device.h") if slab else ("kernels_spmv.hip", "spmv_device.h")
     for f in (*files, "device_common.h"):

@@ -239,6 +239,15 @@ mxe_status mxe_scatter_y(mxe_ctx *ctx, mxe_mat b, int32_t k, const void *Yp, int
  * is reduced by row and the rows cut by a tile edge are joined by a second
  * pass. Never chosen by mxe_tune; force it with mxe_set_variant. */
 #define MXE_VAR_COO     0x500
+/* MXE_VAR_WINDOW with the lanes of MXE_VAR_SLAB (slab size, one-per-CU
+ * flag): the same column-slab layout, plus a window of x held in LDS for each
+ * row block: the widest range of columns that fits the workgroup's LDS beside
+ * its partial sums, placed (once, when first used) where a sample of the
+ * block's stored columns is densest. Entries inside the window read x from
+ * LDS, the others gather it as MXE_VAR_SLAB does. It pays off when a row
+ * block's columns cluster (the unpermuted, mostly diagonal matrices of
+ * Section 7), not after the max-entropy permutation spreads them. */
+#define MXE_VAR_WINDOW  0x600
 #define MXE_VARIANT(family, lanes) ((family) | (lanes))
 
 /* Measures the device's random 8-byte gather rate, the ceiling of a sparse
@@ -306,16 +315,26 @@ mxe_status mxe_batch_destroy(mxe_ctx *ctx, mxe_plan plan);
 
 /* --- serving: continuous batching of requests on resident matrices -------- */
 
+#define MXE_SERVE_MAX_BATCH 64
+
 typedef struct mxe_serve_config {
     int32_t streams;            /* device streams the loop issues on (>= 1) */
     int32_t max_inflight;       /* requests on the device at once (>= 1) */
-    int32_t max_merge_k;        /* merged right-hand sides per launch (1..16) */
+    int32_t max_batch;          /* requests per launch (1..MXE_SERVE_MAX_BATCH) */
 } mxe_serve_config;
 
-/* Starts the serving loop. Requests are admitted while the in-flight bytes
- * (matrix stream plus vectors) stay within the context budget and a slot is
- * free; queued requests on the same matrix are merged into one multi-RHS
- * product up to max_merge_k; work overlaps on `streams` device streams. */
+/* Starts the serving loop (one scheduler thread, `streams` device streams,
+ * and per stream a device descriptor table with its pinned staging copy,
+ * allocated here). Requests are admitted in arrival order while a slot is
+ * free (max_inflight) and the in-flight vector bytes fit the context budget
+ * beside the resident matrices. Each admission round takes up to max_batch
+ * queued requests: the permuted-space ones with k <= 16 become the items of
+ * one persistent launch of mxe_spmv_batch's kernel (each request its own
+ * item, nothing packed or copied), on the least-loaded stream whose table is
+ * free; a round of one request, and original-space or k > 16 requests, run as
+ * their own autotuned products (as mxe_spmv). With max_batch 1 every request
+ * runs exactly as mxe_spmv would run it. Launches on different streams
+ * overlap on the device. */
 mxe_status mxe_serve_start(mxe_ctx *ctx, const mxe_serve_config *cfg);
 /* Serving is Section 1's reuse as a service: matrices are permuted once and
  * stay resident; each request is one product Y = M X (Section 2; Eq. 1 when
@@ -323,8 +342,11 @@ mxe_status mxe_serve_start(mxe_ctx *ctx, const mxe_serve_config *cfg);
  * mxe_spmv. Queues a request and returns its ticket at once (X, Y stay owned
  * by the caller and must stay alive until mxe_wait returns for it; the
  * matrix's own creation, e.g. the stream given to mxe_permute, must be
- * complete). MXE_ERR_INVALID_ARG for a bad request or no running loop,
- * MXE_ERR_NOT_FOUND for an unknown matrix. Thread-safe. */
+ * complete). The first request on a matrix for a k class tunes the matrix
+ * for it and builds the layout a batch runs it on, here in the submitting
+ * thread, so the scheduler only looks them up. MXE_ERR_INVALID_ARG for a bad
+ * request or no running loop, MXE_ERR_NOT_FOUND for an unknown matrix.
+ * Thread-safe. */
 mxe_status mxe_submit(mxe_ctx *ctx, const mxe_item *req, mxe_ticket *out);
 /* The completion side of a Section 1 reuse request (see mxe_submit). Blocks
  * until the request is done (timeout_us < 0: forever). On return other than

@@ -43,17 +43,6 @@ static int vtype_of(mxe_dtype d) { return d == MXE_F64 ? VAL_F64 : d == MXE_F32 
 
 namespace {
 
-struct DeviceGuard {
-    int prev = -1;
-    explicit DeviceGuard(int dev) {
-        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
-        if (prev != dev) (void)hipSetDevice(dev);
-    }
-    ~DeviceGuard() {
-        if (prev >= 0) (void)hipSetDevice(prev);
-    }
-};
-
 // Stream-ordered allocation from the device's pool (freed blocks stay cached).
 struct Scratch {
     void *p = nullptr;
@@ -287,14 +276,50 @@ static mxe_status ensure_slab(mxe_ctx *ctx, Matrix &A, int kclass, int units, in
 }
 
 static void drop_slab(mxe_ctx *ctx, Matrix &A, const Matrix::Slab &sl, hipStream_t s) {
-    const uint64_t bytes = 4ull * slab_offsets_count(sl.g) +
-                           (uint64_t)A.nnz * (4ull + (uint64_t)val_bytes_of(A.storage));
-    for (void *p : {(void *)sl.off, (void *)sl.idx, sl.val}) {
+    uint64_t bytes = 4ull * slab_offsets_count(sl.g) +
+                     (uint64_t)A.nnz * (4ull + (uint64_t)val_bytes_of(A.storage));
+    if (sl.wstart) bytes += 4ull * sl.g.blocks;
+    for (void *p : {(void *)sl.off, (void *)sl.idx, sl.val, (void *)sl.wstart}) {
+        if (!p) continue;
         A.allocs.erase(std::remove(A.allocs.begin(), A.allocs.end(), p), A.allocs.end());
         (void)hipFreeAsync(p, s);
     }
     A.bytes -= bytes;
     ctx->used -= bytes;
+}
+
+// Rows of x (columns of the matrix) the LDS window of a block of layout g
+// holds: what a workgroup's share of its CU's LDS leaves beside the block's
+// partial y and the kernel's own arrays, at most 128 KiB; 0 when under 256.
+static int32_t window_rows(const mxe_ctx *ctx, const SlabGeom &g, int eb) {
+    const int64_t per_cu = std::max<int64_t>(1, (g.blocks + ctx->cu_count - 1) / ctx->cu_count);
+    const int64_t share = std::min<int64_t>((int64_t)ctx->lds_per_cu / per_cu, (int64_t)ctx->lds_per_block);
+    const int64_t avail = share - 8 * 1024 - (int64_t)slab_window_offset(g, eb);
+    const int64_t rows = std::min<int64_t>(avail, 128 * 1024) / ((int64_t)g.kclass * eb);
+    if (rows < 256) return 0;
+    return (int32_t)std::min<int64_t>(rows, g.ncols);
+}
+
+// MXE_VAR_WINDOW: the layout's per-block window starts, built once.
+static mxe_status ensure_window(mxe_ctx *ctx, Matrix &A, Matrix::Slab &sl, hipStream_t s) {
+    if (sl.wstart) return MXE_OK;
+    const int32_t win = window_rows(ctx, sl.g, elem_bytes_of(A.storage));
+    if (win < 1) return fail(MXE_ERR_UNSUPPORTED, "no LDS left for an x window in this layout");
+    const uint64_t bytes = 4ull * sl.g.blocks;
+    mxe_status st;
+    if ((st = reserve(ctx, bytes))) return st;
+    A.bytes += bytes;
+    void *p;
+    if ((st = dev_alloc(A, &p, bytes, s))) return st;
+    MXE_HIP(launch_slab_window(sl.g, A.rp, A.col, win, (int32_t *)p, s));
+    MXE_HIP(hipStreamSynchronize(s));
+    sl.wstart = (int32_t *)p;
+    sl.win = win;
+    return MXE_OK;
+}
+
+static bool slab_family(int variant) {
+    return (variant & 0xf00) == MXE_VAR_SLAB || (variant & 0xf00) == MXE_VAR_WINDOW;
 }
 
 // Arguments for one launch of `variant`, building what the variant needs.
@@ -306,7 +331,7 @@ static mxe_status prepare_args(mxe_ctx *ctx, Matrix &A, int variant, int32_t k, 
     if (family == MXE_VAR_MERGE && (st = ensure_merge(ctx, A, s))) return st;
     if (family == MXE_VAR_COO && (st = ensure_coo(ctx, A, s))) return st;
     *a = make_args(A, k, X, ldx, Y, ldy);
-    if (family == MXE_VAR_SLAB) {
+    if (slab_family(variant)) {
         const Matrix::Slab *sl;
         if ((st = ensure_slab(ctx, A, kclass_of(k), slab_units_of(variant), slab_cus_of(ctx, variant),
                               s, &sl)))
@@ -315,6 +340,12 @@ static mxe_status prepare_args(mxe_ctx *ctx, Matrix &A, int variant, int32_t k, 
         a->slab_off = sl->off;
         a->slab_idx = sl->idx;
         a->slab_val = sl->val;
+        if (family == MXE_VAR_WINDOW) {
+            Matrix::Slab &w = const_cast<Matrix::Slab &>(*sl);
+            if ((st = ensure_window(ctx, A, w, s))) return st;
+            a->slab_wstart = w.wstart;
+            a->slab_win = w.win;
+        }
     }
     return MXE_OK;
 }
@@ -346,6 +377,16 @@ static mxe_status tune(mxe_ctx *ctx, Matrix &A, int32_t k, hipStream_t s, TuneRe
         SlabGeom g;
         if (slab_geometry(A.nrows, A.ncols, kc, vtype_of(A.storage), slab_cus_of(ctx, v),
                           slab_bytes_of(slab_units_of(v)), &g))
+            cands.push_back(v);
+    }
+    // the same layouts with an LDS window of x per row block (one workgroup
+    // per CU leaves the widest window; two per CU, a narrower one)
+    for (int units : {16 | MXE_SLAB_ONE_PER_CU, 32 | MXE_SLAB_ONE_PER_CU, 32}) {
+        const int v = MXE_VARIANT(MXE_VAR_WINDOW, units);
+        SlabGeom g;
+        if (slab_geometry(A.nrows, A.ncols, kc, vtype_of(A.storage), slab_cus_of(ctx, v),
+                          slab_bytes_of(slab_units_of(v)), &g) &&
+            window_rows(ctx, g, (int)eb) > 0)
             cands.push_back(v);
     }
     std::set<std::tuple<int, int, int>> had;          // layouts other work may be using
@@ -428,7 +469,7 @@ static mxe_status tune(mxe_ctx *ctx, Matrix &A, int32_t k, hipStream_t s, TuneRe
     // column-slab layouts built here for this k class and not chosen are freed
     // (stream-ordered after the timing launches)
     for (auto it = A.slabs.begin(); it != A.slabs.end();) {
-        const bool chosen = result == MXE_OK && (r.variant & 0xf00) == MXE_VAR_SLAB &&
+        const bool chosen = result == MXE_OK && slab_family(r.variant) &&
                             std::get<1>(it->first) == slab_units_of(r.variant) &&
                             std::get<2>(it->first) == slab_cus_of(ctx, r.variant);
         if (std::get<0>(it->first) == kc && !had.count(it->first) && !chosen) {
@@ -578,6 +619,8 @@ mxe_status mxe_create(int32_t device, uint64_t hbm_budget_bytes, mxe_ctx **out) 
     ctx->device = device;
     ctx->budget = hbm_budget_bytes;
     ctx->cu_count = prop.multiProcessorCount;
+    ctx->lds_per_cu = prop.maxSharedMemoryPerMultiProcessor;
+    ctx->lds_per_block = prop.sharedMemPerBlock;
     *out = ctx;
     return MXE_OK;
 }
@@ -940,11 +983,11 @@ static mxe_status semiring_core(mxe_ctx *ctx, Matrix &A, int semiring, int32_t k
         TuneResult r;
         mxe_status st = ensure_variant(ctx, A, kc, s, &r);
         if (st) return st;
-        if ((r.variant & 0xf00) == MXE_VAR_SLAB) {
+        if (slab_family(r.variant)) {               // the layout; the window is (+, *) only
             SpmvArgs a;
             if ((st = prepare_args(ctx, A, r.variant, kc, Xc, ldx, Yc, ldy, s, &a))) return st;
             MXE_HIP(launch_spmv_slab(*a.slab, a.vtype, semiring, a.slab_off, a.slab_idx, a.slab_val,
-                                     kc, Xc, ldx, Yc, ldy, s));
+                                     kc, Xc, ldx, Yc, ldy, nullptr, 0, s));
         } else {
             MXE_HIP(launch_spmv_semiring(make_args(A, kc, Xc, ldx, Yc, ldy), semiring, s));
         }
@@ -1081,9 +1124,10 @@ mxe_status mxe_set_variant(mxe_ctx *ctx, mxe_mat m, int32_t k, int32_t variant) 
     if ((family == MXE_VAR_GROUP || family == MXE_VAR_FIXED) && !pow2)
         return fail(MXE_ERR_INVALID_ARG, "lanes must be 1..64, a power of two");
     if (family != MXE_VAR_GROUP && family != MXE_VAR_BINNED && family != MXE_VAR_MERGE &&
-        family != MXE_VAR_SLAB && family != MXE_VAR_FIXED && family != MXE_VAR_COO)
+        family != MXE_VAR_SLAB && family != MXE_VAR_FIXED && family != MXE_VAR_COO &&
+        family != MXE_VAR_WINDOW)
         return fail(MXE_ERR_INVALID_ARG, "unknown variant family");
-    if (family == MXE_VAR_SLAB) {
+    if (slab_family(variant)) {
         SlabGeom sg;
         const int units = slab_units_of(variant);
         if (units < 1 || units > 64)
@@ -1091,29 +1135,65 @@ mxe_status mxe_set_variant(mxe_ctx *ctx, mxe_mat m, int32_t k, int32_t variant) 
         if (!slab_geometry(A->nrows, A->ncols, kclass_of(k), vtype_of(A->storage),
                            slab_cus_of(ctx, variant), slab_bytes_of(units), &sg))
             return fail(MXE_ERR_UNSUPPORTED, "column-slab layout does not fit this matrix");
+        if (family == MXE_VAR_WINDOW && window_rows(ctx, sg, elem_bytes_of(A->storage)) < 1)
+            return fail(MXE_ERR_UNSUPPORTED, "no LDS left for an x window in this layout");
     }
     if (family == MXE_VAR_MERGE && kclass_of(k) > 4)
         return fail(MXE_ERR_UNSUPPORTED, "merge-path variant handles k <= 4");
-    TuneResult r{variant, family == MXE_VAR_GROUP ? lanes : 8};
+    TuneResult r{variant, family == MXE_VAR_GROUP ? lanes : 8, true};
     auto it = ctx->tuned.find(key);
     if (it != ctx->tuned.end() && family != MXE_VAR_GROUP) r.group_lanes = it->second.group_lanes;
     ctx->tuned[key] = r;
     return MXE_OK;
 }
 
+}  // extern "C"
+
 // ---- batches ------------------------------------------------------------------------
 
-// work units of one batch item: its slab layout's blocks, or row tiles
-static int64_t batch_units(const BatchDesc &d) {
+namespace mxe {
+
+// work units of one whole batch item: its slab layout's blocks, or row tiles
+static int64_t item_units(const BatchDesc &d) {
     return d.slab_off ? d.slab.blocks : (d.nrows + d.rows_per_tile - 1) / d.rows_per_tile;
 }
 
-// Deals the matrices to the per-XCD queues: largest first (bytes one product
-// moves) onto the least loaded queue, so each XCD's share is balanced and its
-// matrices' x stays in its own L2. Each queue lists its matrices in item
-// order, with tile_begin counted within the queue.
-static void assign_queues(std::vector<BatchDesc> &descs, const std::vector<uint64_t> &cost,
+// Deals the items to the per-XCD queues: largest first (bytes one product
+// moves) onto the least loaded queue, so each XCD's share is balanced and an
+// item's x stays in its own L2. An item moving more than 1/kBatchQueues of the
+// batch's bytes would leave its queue the last to finish whatever the others
+// hold, so it is first cut into pieces of consecutive work units, each at most
+// 1/(2 kBatchQueues) of the bytes (its x is then fetched once per piece's XCD).
+// Each queue lists its pieces in item order, with tile_begin counted within
+// the queue.
+static void assign_queues(std::vector<BatchDesc> &descs, std::vector<uint64_t> &cost,
                           std::vector<int32_t> &qent, BatchQueues &qs) {
+    uint64_t total = 0;
+    for (uint64_t c : cost) total += c;
+    const size_t items = descs.size();
+    for (size_t i = 0; i < items; ++i) {
+        const int64_t units = descs[i].units;
+        if (units < 2 || cost[i] * kBatchQueues <= total) continue;
+        // rounded up, so the pieces number at most count + kBatchExtraPieces
+        const uint64_t limit = std::max<uint64_t>(1, (total + kBatchExtraPieces - 1) / kBatchExtraPieces);
+        const int64_t pieces = std::min<int64_t>(units, (int64_t)((cost[i] + limit - 1) / limit));
+        const BatchDesc whole = descs[i];
+        const uint64_t c = cost[i];
+        for (int64_t p = 0; p < pieces; ++p) {
+            const int64_t u0 = units * p / pieces, u1 = units * (p + 1) / pieces;
+            BatchDesc d = whole;
+            d.unit0 = (int32_t)u0;
+            d.units = (int32_t)(u1 - u0);
+            const uint64_t pc = (uint64_t)((double)c * (double)(u1 - u0) / (double)units);
+            if (p == 0) {
+                descs[i] = d;
+                cost[i] = pc;
+            } else {
+                descs.push_back(d);
+                cost.push_back(pc);
+            }
+        }
+    }
     const int32_t n = (int32_t)descs.size();
     std::vector<int32_t> order(n), queue_of(n);
     for (int32_t i = 0; i < n; ++i) order[i] = i;
@@ -1132,7 +1212,7 @@ static void assign_queues(std::vector<BatchDesc> &descs, const std::vector<uint6
         for (int32_t i = 0; i < n; ++i) {
             if (queue_of[i] != q) continue;
             descs[i].tile_begin = (int32_t)tiles;
-            tiles += batch_units(descs[i]);
+            tiles += descs[i].units;
             qent.push_back(i);
         }
         qs.qtiles[q] = (int32_t)tiles;
@@ -1140,54 +1220,76 @@ static void assign_queues(std::vector<BatchDesc> &descs, const std::vector<uint6
     qs.qbegin[kBatchQueues] = (int32_t)qent.size();
 }
 
-// One desc per item. An item whose tuned variant is the column-slab kernel
-// runs as the blocks of that layout, any other as row tiles with its tuned
-// GROUP lane count. lds: the dynamic LDS the launch needs (the largest slab
-// block's partial y).
-static mxe_status build_descs(mxe_ctx *ctx, int32_t count, const mxe_item *items, hipStream_t s,
-                              std::vector<BatchDesc> &descs, std::vector<int32_t> &qent,
-                              BatchQueues &qs, size_t *lds) {
-    if (count < 1 || !items) return fail(MXE_ERR_INVALID_ARG, "empty batch");
-    descs.clear();
-    *lds = 0;
-    std::vector<uint64_t> cost;
-    int64_t tiles = 0;
-    for (int32_t i = 0; i < count; ++i) {
-        const mxe_item &it = items[i];
-        auto A = find_matrix(ctx, it.mat);
-        if (!A) return fail(MXE_ERR_NOT_FOUND, "unknown matrix handle in batch");
-        if (it.flags != MXE_SPACE_PERMUTED)
-            return fail(MXE_ERR_UNSUPPORTED, "batches take permuted-space vectors only");
-        if (it.k > 16) return fail(MXE_ERR_UNSUPPORTED, "batches take k <= 16");
-        mxe_status st = check_dense(*A, it.k, it.X, it.ldx, it.Y, it.ldy);
-        if (st) return st;
-        TuneResult r;
-        if ((st = ensure_variant(ctx, *A, it.k, s, &r))) return st;
-        BatchDesc d{};
-        d.rp = A->rp;
-        d.col = A->col;
-        d.val = A->val;
-        d.X = it.X;
-        d.Y = it.Y;
-        d.ldx = it.ldx;
-        d.ldy = it.ldy;
-        d.nrows = A->nrows;
-        d.k = it.k;
-        d.vtype = vtype_of(A->storage);
-        d.kclass = kclass_of(it.k);
-        d.lanes = std::max(r.group_lanes, d.kclass);   // set_variant may force fewer
-        d.rows_per_tile = (kBatchBlock / d.lanes) * 2;
-        if ((r.variant & 0xf00) == MXE_VAR_SLAB) {
-            // the item's x is gathered by one XCD's workgroups: a layout with
-            // row blocks sized for them (fewer, larger blocks, so fewer slab
-            // phases per row), else the tuned layout
-            const Matrix::Slab *sl;
-            const int xcd_cus = std::max(1, ctx->cu_count / kBatchQueues);
-            const int units = slab_units_of(r.variant);
-            if (ensure_slab(ctx, *A, d.kclass, units, xcd_cus, s, &sl) != MXE_OK &&
-                (st = ensure_slab(ctx, *A, d.kclass, units, slab_cus_of(ctx, r.variant), s, &sl)))
-                return st;
-            const int eb = elem_bytes_of(A->storage);
+// slab size (in 64 KiB of x) of the batch layout for an item not tuned to the slab kernel
+constexpr int kBatchSlabUnits = 16;
+
+// One desc per item (before pieces), each item's work unit chosen by the
+// batch itself: the blocks of a column-slab layout whose row blocks are sized
+// for one XCD's CUs (the item's x is gathered by one XCD) with the tuned slab
+// size, or 1 MiB of x for an item tuned to a row kernel; a slab-tuned item
+// falls back to its tuned layout, any other to row tiles of its tuned GROUP
+// lane count, when that layout does not fit the matrix or the HBM budget. An
+// item whose variant was forced to a row family (mxe_set_variant) runs as row
+// tiles. lds: the dynamic LDS the launch needs (the largest slab block's
+// partial y).
+mxe_status batch_item_desc(mxe_ctx *ctx, Matrix &A, const mxe_item &it, int32_t index,
+                           hipStream_t s, bool prepare, BatchDesc *out, size_t *lds) {
+    if (it.flags != MXE_SPACE_PERMUTED)
+        return fail(MXE_ERR_UNSUPPORTED, "batches take permuted-space vectors only");
+    if (it.k > 16) return fail(MXE_ERR_UNSUPPORTED, "batches take k <= 16");
+    mxe_status st = check_dense(A, it.k, it.X, it.ldx, it.Y, it.ldy);
+    if (st) return st;
+    TuneResult r;
+    if (prepare) {
+        if ((st = ensure_variant(ctx, A, it.k, s, &r))) return st;
+    } else {
+        auto tr = ctx->tuned.find(tune_key(A, it.k));
+        if (tr == ctx->tuned.end())
+            return fail(MXE_ERR_UNSUPPORTED, "batch item " + std::to_string(index) +
+                                                 " is not tuned for its k yet");
+        r = tr->second;
+    }
+    BatchDesc d{};
+    d.rp = A.rp;
+    d.col = A.col;
+    d.val = A.val;
+    d.X = it.X;
+    d.Y = it.Y;
+    d.ldx = it.ldx;
+    d.ldy = it.ldy;
+    d.nrows = A.nrows;
+    d.k = it.k;
+    d.vtype = vtype_of(A.storage);
+    d.kclass = kclass_of(it.k);
+    d.lanes = std::max(r.group_lanes, d.kclass);   // set_variant may force fewer
+    d.rows_per_tile = (kBatchBlock / d.lanes) * 2;
+    const bool slab_tuned = slab_family(r.variant);
+    if (slab_tuned || !r.forced) {
+        const int xcd_cus = std::max(1, ctx->cu_count / kBatchQueues);
+        const int units = slab_tuned ? slab_units_of(r.variant) : kBatchSlabUnits;
+        std::vector<int> cus{xcd_cus};
+        if (slab_tuned) cus.push_back(slab_cus_of(ctx, r.variant));
+        const Matrix::Slab *sl = nullptr;
+        for (int c : cus) {
+            if (prepare) {
+                if ((st = ensure_slab(ctx, A, d.kclass, units, c, s, &sl)) == MXE_OK) break;
+                sl = nullptr;
+            } else {
+                // the layout a preparing call would have picked, if it was built
+                auto f = A.slabs.find(std::make_tuple(d.kclass, units, c));
+                if (f != A.slabs.end()) {
+                    sl = &f->second;
+                    break;
+                }
+            }
+        }
+        if (!sl && slab_tuned) {
+            if (prepare) return st;
+            return fail(MXE_ERR_UNSUPPORTED, "batch item " + std::to_string(index) +
+                                                 " has no slab layout built yet");
+        }
+        if (sl) {
+            const int eb = elem_bytes_of(A.storage);
             d.slab = sl->g;
             d.slab_off = sl->off;
             d.slab_idx = sl->idx;
@@ -1195,21 +1297,46 @@ static mxe_status build_descs(mxe_ctx *ctx, int32_t count, const mxe_item *items
             d.vec_x = slab_vec_x(d.kclass, it.k, it.X, it.ldx, eb) ? 1 : 0;
             *lds = std::max(*lds, (size_t)sl->g.rows_per_block * d.kclass * eb);
         }
-        tiles += batch_units(d);
+    }
+    d.unit0 = 0;
+    d.units = (int32_t)item_units(d);
+    d.item = index;
+    *out = d;
+    return MXE_OK;
+}
+
+mxe_status build_batch_descs(mxe_ctx *ctx, int32_t count, const mxe_item *items, hipStream_t s,
+                             bool prepare, std::vector<BatchDesc> &descs,
+                             std::vector<int32_t> &qent, BatchQueues &qs, size_t *lds) {
+    if (count < 1 || !items) return fail(MXE_ERR_INVALID_ARG, "empty batch");
+    descs.clear();
+    *lds = 0;
+    std::vector<uint64_t> cost;
+    int64_t tiles = 0;
+    for (int32_t i = 0; i < count; ++i) {
+        auto A = find_matrix(ctx, items[i].mat);
+        if (!A) return fail(MXE_ERR_NOT_FOUND, "unknown matrix handle in batch");
+        BatchDesc d;
+        mxe_status st = batch_item_desc(ctx, *A, items[i], i, s, prepare, &d, lds);
+        if (st) return st;
+        tiles += d.units;
         if (tiles > INT32_MAX) return fail(MXE_ERR_UNSUPPORTED, "too many tiles in batch");
         descs.push_back(d);
-        cost.push_back(request_bytes(*A, it.k));
+        cost.push_back(request_bytes(*A, items[i].k));
     }
     assign_queues(descs, cost, qent, qs);
     return MXE_OK;
 }
 
-// the value type every item shares, or -1 (the persistent kernel then carries every path)
-static int common_vtype(const std::vector<BatchDesc> &descs) {
+int batch_common_vtype(const std::vector<BatchDesc> &descs) {
     for (const BatchDesc &d : descs)
         if (d.vtype != descs[0].vtype) return -1;
     return descs.empty() ? -1 : descs[0].vtype;
 }
+
+}  // namespace mxe
+
+extern "C" {
 
 mxe_status mxe_spmv_batch(mxe_ctx *ctx, int32_t count, const mxe_item *items, void *stream) {
     if (!ctx) return fail(MXE_ERR_INVALID_ARG, "ctx is NULL");
@@ -1220,9 +1347,9 @@ mxe_status mxe_spmv_batch(mxe_ctx *ctx, int32_t count, const mxe_item *items, vo
     std::vector<int32_t> qent;
     BatchQueues qs{};
     size_t lds = 0;
-    mxe_status st = build_descs(ctx, count, items, s, descs, qent, qs, &lds);
+    mxe_status st = build_batch_descs(ctx, count, items, s, true, descs, qent, qs, &lds);
     if (st) return st;
-    const int vt = common_vtype(descs);
+    const int vt = batch_common_vtype(descs);
     const int32_t grid = batch_grid_size(vt, lds);
     if (grid < 1) return fail(MXE_ERR_DEVICE, "batch kernel occupancy query failed");
     Scratch dd, ctr;
@@ -1246,10 +1373,10 @@ mxe_status mxe_batch_create(mxe_ctx *ctx, int32_t count, const mxe_item *items, 
     std::lock_guard<std::recursive_mutex> lk(ctx->mu);
     DeviceGuard g(ctx->device);
     auto plan = std::make_unique<Plan>();
-    mxe_status st = build_descs(ctx, count, items, nullptr, plan->descs, plan->qent, plan->queues,
-                                &plan->lds);
+    mxe_status st = build_batch_descs(ctx, count, items, nullptr, true, plan->descs, plan->qent,
+                                      plan->queues, &plan->lds);
     if (st) return st;
-    plan->vtype = common_vtype(plan->descs);
+    plan->vtype = batch_common_vtype(plan->descs);
     plan->grid = batch_grid_size(plan->vtype, plan->lds);
     if (plan->grid < 1) return fail(MXE_ERR_DEVICE, "batch kernel occupancy query failed");
     plan->items.assign(items, items + count);
@@ -1298,20 +1425,19 @@ mxe_status mxe_batch_launch(mxe_ctx *ctx, mxe_plan h, const mxe_item *items, voi
             if (st) return st;
         }
         bool changed = false;
-        for (size_t i = 0; i < p.items.size(); ++i) {
-            BatchDesc &d = p.descs[i];
-            if (d.X != items[i].X || d.Y != items[i].Y || d.ldx != items[i].ldx ||
-                d.ldy != items[i].ldy) {
-                d.X = items[i].X;
-                d.Y = items[i].Y;
-                d.ldx = items[i].ldx;
-                d.ldy = items[i].ldy;
+        for (BatchDesc &d : p.descs) {                  // every piece of every item
+            const mxe_item &a = items[d.item];
+            if (d.X != a.X || d.Y != a.Y || d.ldx != a.ldx || d.ldy != a.ldy) {
+                d.X = a.X;
+                d.Y = a.Y;
+                d.ldx = a.ldx;
+                d.ldy = a.ldy;
                 if (d.slab_off)
                     d.vec_x = slab_vec_x(d.kclass, d.k, d.X, d.ldx, d.vtype == VAL_F64 ? 8 : 4) ? 1 : 0;
                 changed = true;
             }
-            p.items[i] = items[i];
         }
+        for (size_t i = 0; i < p.items.size(); ++i) p.items[i] = items[i];
         if (changed) {
             // the pinned staging copy is free once the previous rewrite ran;
             // the rewrite itself waits on the device for the previous replay

@@ -121,10 +121,22 @@ inline bool slab_vec_x(int kclass, int32_t k, const void *X, int64_t ldx, int el
     return kclass > 1 && k == kclass && (ldx * elem_bytes) % 16 == 0 &&
            (reinterpret_cast<uintptr_t>(X) % 16) == 0;
 }
-// semiring: MXE_SR_* (mxe.h)
+// The x window of MXE_VAR_WINDOW: in a block's dynamic LDS, after its partial
+// y (rows_per_block x kclass values of elem_bytes), 16-byte aligned.
+__host__ __device__ inline size_t slab_window_offset(const SlabGeom &g, int elem_bytes) {
+    return ((size_t)g.rows_per_block * g.kclass * elem_bytes + 15) / 16 * 16;
+}
+// wstart (device, g.blocks int32): each block's window start for windows of
+// win columns (x rows).
+hipError_t launch_slab_window(const SlabGeom &g, const int32_t *rp, const int32_t *col, int32_t win,
+                              int32_t *wstart, hipStream_t s);
+// semiring: MXE_SR_* (mxe.h). win > 0 (plus semiring (+, *)): each block
+// reads x rows [wstart[b], wstart[b] + win) from an LDS copy (MXE_VAR_WINDOW);
+// the dynamic LDS then grows by win x kclass values.
 hipError_t launch_spmv_slab(const SlabGeom &g, int vtype, int semiring, const int32_t *off,
                             const uint32_t *idx, const void *val, int32_t k, const void *X,
-                            int64_t ldx, void *Y, int64_t ldy, hipStream_t s);
+                            int64_t ldx, void *Y, int64_t ldy, const int32_t *wstart, int32_t win,
+                            hipStream_t s);
 
 struct SpmvArgs {
     int32_t nrows, ncols;
@@ -151,6 +163,9 @@ struct SpmvArgs {
     const int32_t *slab_off;
     const uint32_t *slab_idx;
     const void *slab_val;
+    // window variant: per-block window starts and the window's rows of x
+    const int32_t *slab_wstart;
+    int32_t slab_win;
     // COO variant: row index per entry (built once, read only)
     const int32_t *coo_row;
 };
@@ -168,7 +183,7 @@ hipError_t launch_coo_rows(int32_t nrows, const int32_t *rp, int32_t *row, hipSt
 hipError_t launch_spmv(const SpmvArgs &a, int variant, hipStream_t s);
 
 // ---- batched persistent SpMV ------------------------------------------------
-struct BatchDesc {             // one matrix of a batch (device-resident table)
+struct BatchDesc {             // one piece of one batch item (device-resident table)
     const int32_t *rp, *col;
     const void *val;
     const void *X;
@@ -179,7 +194,9 @@ struct BatchDesc {             // one matrix of a batch (device-resident table)
     int32_t kclass;            // k rounded up to a power of two
     int32_t lanes;             // row tiles: lanes per row (1..64), >= kclass
     int32_t rows_per_tile;     // row tiles: rows one work unit covers
-    int32_t tile_begin;        // first work unit of this matrix within its queue
+    int32_t tile_begin;        // first work unit of this piece within its queue
+    int32_t unit0, units;      // the piece: the item's work units [unit0, unit0 + units)
+    int32_t item;              // index of the item in the batch
     int32_t vec_x;             // slab units: whole X rows as 16-byte loads (slab_vec_x)
     // slab units (slab_off non-null): one work unit per block of this layout
     // for k class kclass, in place of row tiles
@@ -188,10 +205,14 @@ struct BatchDesc {             // one matrix of a batch (device-resident table)
     const uint32_t *slab_idx;
     const void *slab_val;
 };
-// One work queue per XCD: queue q holds the matrices qent[qbegin[q] ..
+// One work queue per XCD: queue q holds the pieces qent[qbegin[q] ..
 // qbegin[q+1]) (indices into the desc table, in unit order) and qtiles[q]
 // work units in all.
 constexpr int kBatchQueues = 8;
+// An item moving more than 1/kBatchQueues of a batch's bytes is cut into
+// pieces of at most 1/(2 kBatchQueues) of them, so a batch of n items has at
+// most n + 2 kBatchQueues pieces.
+constexpr int kBatchExtraPieces = 2 * kBatchQueues;
 struct BatchQueues {
     int32_t qbegin[kBatchQueues + 1];
     int32_t qtiles[kBatchQueues];

@@ -1,11 +1,12 @@
 // Many matrices in one persistent launch (the reuse setting of Section 1:
 // resident, already permuted matrices multiplied again and again).
 //
-// Each item of a batch is cut into work units: the blocks of its column-slab
-// layout when its tuned variant is the slab kernel, else row tiles. The units
-// sit in one queue per XCD (workgroups are dealt to the 8 XCDs round-robin);
-// the host deals whole items to the queues, largest first onto the least
-// loaded, so an item's x is gathered by one XCD and stays in that XCD's L2.
+// Each item of a batch is cut into work units: the blocks of a column-slab
+// layout, or row tiles. The units sit in one queue per XCD (workgroups are
+// dealt to the 8 XCDs round-robin); the host deals items (or, for an item too
+// large for one queue, pieces of consecutive units) to the queues, largest
+// first onto the least loaded, so an item's x is gathered by one XCD and
+// stays in that XCD's L2.
 // A workgroup of 1024 threads takes units from its own XCD's queue and, once
 // that is empty, from the other queues in turn. Every pull either returns a
 // unit or finds a queue exhausted, and each workgroup stops after finding all
@@ -87,7 +88,7 @@ __global__ __launch_bounds__(kBatchBlock) void k_spmv_batch(const BatchDesc *__r
             else hi = mid - 1;
         }
         const BatchDesc &d = descs[qent[lo]];
-        const int32_t u = unit - d.tile_begin;
+        const int32_t u = unit - d.tile_begin + d.unit0;
         if constexpr (VT == VAL_F64) {
             batch_unit<double, double>(d, u, q, smem, soff);
         } else if constexpr (VT == VAL_F32) {

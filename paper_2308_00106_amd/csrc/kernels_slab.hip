@@ -96,7 +96,10 @@ __global__ __launch_bounds__(kSlabBlock) void k_slab_fill(SlabGeom g, const int3
                                          (int64_t)(blockIdx.x + 1) * g.rows_per_block), g.nrows);
     const int32_t nr = r0 < r1 ? (int32_t)(r1 - r0) : 0;
     int32_t *wrp = rps + wave * (g.rows_per_sub + 1);
-    for (int32_t i = lane; i <= nr; i += kWave) wrp[i] = rp[r0 + i];
+    // a wavefront of the last block may own no rows (r0 past the last row):
+    // it reads nothing, rp[r0] would lie beyond the array
+    if (nr > 0)
+        for (int32_t i = lane; i <= nr; i += kWave) wrp[i] = rp[r0 + i];
     __syncthreads();
     if (nr == 0) return;
     const double inv_w = 1.0 / g.width;
@@ -148,39 +151,60 @@ __global__ __launch_bounds__(kSlabBlock) void k_slab_fill(SlabGeom g, const int3
     }
 }
 
-// The product: one layout block per workgroup (slab_block).
-template <typename V, typename T, int KM, int SR>
+// The product: one layout block per workgroup (slab_block). WIN: the
+// block's x window (wstart[block], win rows) sits in LDS after the partial y.
+template <typename V, typename T, int KM, int SR, bool WIN>
 __global__ __launch_bounds__(kSlabBlock) void k_spmv_slab(SlabGeom g, const int32_t *__restrict__ off,
                                                           const uint32_t *__restrict__ idx,
                                                           const V *__restrict__ val, int32_t k,
                                                           const T *__restrict__ X, int64_t ldx,
                                                           T *__restrict__ Y, int64_t ldy,
-                                                          int vec_x) {
-    extern __shared__ unsigned char smem[];
+                                                          int vec_x, const int32_t *__restrict__ wstart,
+                                                          int32_t win) {
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     __shared__ int32_t soff[kSubBlocks][kSlabMax + 1];
-    slab_block<V, T, KM, SR>(g, blockIdx.x, blockIdx.x % 8, off, idx, val, k, X, ldx, Y, ldy, vec_x,
-                             reinterpret_cast<T *>(smem), soff, threadIdx.x);
+    T *yp = reinterpret_cast<T *>(smem);
+    if constexpr (WIN) {
+        T *xw = yp + slab_window_offset(g, (int)sizeof(T)) / sizeof(T);
+        slab_block<V, T, KM, SR, true>(g, blockIdx.x, blockIdx.x % 8, off, idx, val, k, X, ldx, Y,
+                                       ldy, vec_x, yp, soff, threadIdx.x, xw, wstart[blockIdx.x], win);
+    } else {
+        slab_block<V, T, KM, SR>(g, blockIdx.x, blockIdx.x % 8, off, idx, val, k, X, ldx, Y, ldy,
+                                 vec_x, yp, soff, threadIdx.x);
+    }
 }
 
 template <typename V, typename T, int KM, int SR>
 hipError_t slab_launch(const SlabGeom &g, const int32_t *off, const uint32_t *idx, const void *val,
-                       int32_t k, const void *X, int64_t ldx, void *Y, int64_t ldy, hipStream_t s) {
-    const size_t lds = (size_t)g.rows_per_block * KM * sizeof(T);
+                       int32_t k, const void *X, int64_t ldx, void *Y, int64_t ldy,
+                       const int32_t *wstart, int32_t win, hipStream_t s) {
+    size_t lds = (size_t)g.rows_per_block * KM * sizeof(T);
     const int vec_x = slab_vec_x(KM, k, X, ldx, (int)sizeof(T));
-    hipLaunchKernelGGL((k_spmv_slab<V, T, KM, SR>), dim3(g.blocks), dim3(kSlabBlock), lds, s, g, off,
-                       idx, (const V *)val, k, (const T *)X, ldx, (T *)Y, ldy, vec_x);
+    if constexpr (SR == 0) {
+        if (win > 0) {
+            lds = slab_window_offset(g, (int)sizeof(T)) + (size_t)win * KM * sizeof(T);
+            hipLaunchKernelGGL((k_spmv_slab<V, T, KM, SR, true>), dim3(g.blocks), dim3(kSlabBlock),
+                               lds, s, g, off, idx, (const V *)val, k, (const T *)X, ldx, (T *)Y,
+                               ldy, vec_x, wstart, win);
+            return hipGetLastError();
+        }
+    }
+    hipLaunchKernelGGL((k_spmv_slab<V, T, KM, SR, false>), dim3(g.blocks), dim3(kSlabBlock), lds, s,
+                       g, off, idx, (const V *)val, k, (const T *)X, ldx, (T *)Y, ldy, vec_x,
+                       (const int32_t *)nullptr, 0);
     return hipGetLastError();
 }
 
 template <typename V, typename T, int SR>
 hipError_t slab_by_k(const SlabGeom &g, const int32_t *off, const uint32_t *idx, const void *val,
-                     int32_t k, const void *X, int64_t ldx, void *Y, int64_t ldy, hipStream_t s) {
+                     int32_t k, const void *X, int64_t ldx, void *Y, int64_t ldy,
+                     const int32_t *wstart, int32_t win, hipStream_t s) {
     switch (g.kclass) {
-    case 1: return slab_launch<V, T, 1, SR>(g, off, idx, val, k, X, ldx, Y, ldy, s);
-    case 2: return slab_launch<V, T, 2, SR>(g, off, idx, val, k, X, ldx, Y, ldy, s);
-    case 4: return slab_launch<V, T, 4, SR>(g, off, idx, val, k, X, ldx, Y, ldy, s);
-    case 8: return slab_launch<V, T, 8, SR>(g, off, idx, val, k, X, ldx, Y, ldy, s);
-    case 16: return slab_launch<V, T, 16, SR>(g, off, idx, val, k, X, ldx, Y, ldy, s);
+    case 1: return slab_launch<V, T, 1, SR>(g, off, idx, val, k, X, ldx, Y, ldy, wstart, win, s);
+    case 2: return slab_launch<V, T, 2, SR>(g, off, idx, val, k, X, ldx, Y, ldy, wstart, win, s);
+    case 4: return slab_launch<V, T, 4, SR>(g, off, idx, val, k, X, ldx, Y, ldy, wstart, win, s);
+    case 8: return slab_launch<V, T, 8, SR>(g, off, idx, val, k, X, ldx, Y, ldy, wstart, win, s);
+    case 16: return slab_launch<V, T, 16, SR>(g, off, idx, val, k, X, ldx, Y, ldy, wstart, win, s);
     default: return hipErrorInvalidValue;
     }
 }
@@ -188,12 +212,71 @@ hipError_t slab_by_k(const SlabGeom &g, const int32_t *off, const uint32_t *idx,
 template <typename V, typename T>
 hipError_t slab_by_semiring(const SlabGeom &g, int semiring, const int32_t *off, const uint32_t *idx,
                             const void *val, int32_t k, const void *X, int64_t ldx, void *Y,
-                            int64_t ldy, hipStream_t s) {
+                            int64_t ldy, const int32_t *wstart, int32_t win, hipStream_t s) {
     switch (semiring) {
-    case 0: return slab_by_k<V, T, 0>(g, off, idx, val, k, X, ldx, Y, ldy, s);
-    case 1: return slab_by_k<V, T, 1>(g, off, idx, val, k, X, ldx, Y, ldy, s);
-    case 2: return slab_by_k<V, T, 2>(g, off, idx, val, k, X, ldx, Y, ldy, s);
+    case 0: return slab_by_k<V, T, 0>(g, off, idx, val, k, X, ldx, Y, ldy, wstart, win, s);
+    case 1: return slab_by_k<V, T, 1>(g, off, idx, val, k, X, ldx, Y, ldy, nullptr, 0, s);
+    case 2: return slab_by_k<V, T, 2>(g, off, idx, val, k, X, ldx, Y, ldy, nullptr, 0, s);
     default: return hipErrorInvalidValue;
+    }
+}
+
+// Window placement: block b's window starts where the most of a sample of
+// its stored columns fit into `win` consecutive columns. Up to 1024 entries
+// spread evenly over the block's rows are sampled (all of them when fewer),
+// sorted in LDS (bitonic network), and each sample i counts the samples in
+// [s_i, s_i + win); the first sample with the largest count gives the start,
+// moved left when the window would pass the last column.
+constexpr int kWinSample = kSlabBlock;
+__global__ __launch_bounds__(kSlabBlock) void k_slab_window(SlabGeom g, const int32_t *__restrict__ rp,
+                                                            const int32_t *__restrict__ col,
+                                                            int32_t win, int32_t *__restrict__ wstart) {
+    __shared__ int32_t smp[kWinSample];
+    __shared__ int64_t best[kSlabBlock / kWave];
+    const int t = threadIdx.x;
+    const int64_t r0 = (int64_t)blockIdx.x * g.rows_per_block;
+    const int64_t r1 = std::min<int64_t>(r0 + g.rows_per_block, g.nrows);
+    const int64_t e0 = rp[r0], n = rp[r1] - e0;
+    const int cnt = (int)std::min<int64_t>(n, kWinSample);
+    smp[t] = t < cnt ? col[e0 + (int64_t)t * n / cnt] : INT32_MAX;
+    __syncthreads();
+    for (int kk = 2; kk <= kWinSample; kk <<= 1)
+        for (int j = kk >> 1; j > 0; j >>= 1) {
+            const int p = t ^ j;
+            if (p > t) {
+                const int32_t a = smp[t], b = smp[p];
+                if ((a > b) == ((t & kk) == 0)) {
+                    smp[t] = b;
+                    smp[p] = a;
+                }
+            }
+            __syncthreads();
+        }
+    // key: count in the high bits, then the lower sample index first
+    int64_t key = -1;
+    if (t < cnt) {
+        const int64_t lim = (int64_t)smp[t] + win;          // first column past the window
+        int lo = t, hi = cnt;                                // first sample >= lim
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (smp[mid] < lim) lo = mid + 1;
+            else hi = mid;
+        }
+        key = ((int64_t)(lo - t) << 32) | (uint32_t)(kWinSample - t);
+    }
+    for (int o = kWave / 2; o > 0; o >>= 1) {
+        const int64_t other = __shfl_xor(key, o);
+        key = other > key ? other : key;
+    }
+    if (t % kWave == 0) best[t / kWave] = key;
+    __syncthreads();
+    if (t == 0) {
+        int64_t b = best[0];
+        for (int w = 1; w < kSlabBlock / kWave; ++w) b = best[w] > b ? best[w] : b;
+        int64_t start = 0;
+        if (b >= 0) start = smp[kWinSample - (int)(b & 0xffffffff)];
+        if (start + win > g.ncols) start = std::max<int64_t>(0, (int64_t)g.ncols - win);
+        wstart[blockIdx.x] = (int32_t)start;
     }
 }
 
@@ -264,14 +347,26 @@ hipError_t launch_slab_build(const SlabGeom &g, const int32_t *rp, const int32_t
     return hipGetLastError();
 }
 
+hipError_t launch_slab_window(const SlabGeom &g, const int32_t *rp, const int32_t *col, int32_t win,
+                              int32_t *wstart, hipStream_t s) {
+    if (win < 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_slab_window, dim3(g.blocks), dim3(kSlabBlock), 0, s, g, rp, col, win, wstart);
+    return hipGetLastError();
+}
+
 hipError_t launch_spmv_slab(const SlabGeom &g, int vtype, int semiring, const int32_t *off,
                             const uint32_t *idx, const void *val, int32_t k, const void *X,
-                            int64_t ldx, void *Y, int64_t ldy, hipStream_t s) {
-    if (k > g.kclass) return hipErrorInvalidValue;
+                            int64_t ldx, void *Y, int64_t ldy, const int32_t *wstart, int32_t win,
+                            hipStream_t s) {
+    if (k > g.kclass || win < 0 || (win > 0 && !wstart)) return hipErrorInvalidValue;
     switch (vtype) {
-    case VAL_F64: return slab_by_semiring<double, double>(g, semiring, off, idx, val, k, X, ldx, Y, ldy, s);
-    case VAL_F32: return slab_by_semiring<float, float>(g, semiring, off, idx, val, k, X, ldx, Y, ldy, s);
-    case VAL_BF16: return slab_by_semiring<uint16_t, float>(g, semiring, off, idx, val, k, X, ldx, Y, ldy, s);
+    case VAL_F64:
+        return slab_by_semiring<double, double>(g, semiring, off, idx, val, k, X, ldx, Y, ldy, wstart, win, s);
+    case VAL_F32:
+        return slab_by_semiring<float, float>(g, semiring, off, idx, val, k, X, ldx, Y, ldy, wstart, win, s);
+    case VAL_BF16:
+        return slab_by_semiring<uint16_t, float>(g, semiring, off, idx, val, k, X, ldx, Y, ldy, wstart,
+                                                 win, s);
     default: return hipErrorInvalidValue;
     }
 }

@@ -678,10 +678,13 @@ hipError_t launch_coo_rows(int32_t nrows, const int32_t *rp, int32_t *row, hipSt
 
 hipError_t launch_spmv(const SpmvArgs &a, int variant, hipStream_t s) {
     if (a.nrows <= 0) return hipSuccess;
-    if ((variant & 0xf00) == MXE_VAR_SLAB) {
+    if ((variant & 0xf00) == MXE_VAR_SLAB || (variant & 0xf00) == MXE_VAR_WINDOW) {
         if (!a.slab) return hipErrorInvalidValue;
+        const bool win = (variant & 0xf00) == MXE_VAR_WINDOW;
+        if (win && (!a.slab_wstart || a.slab_win < 1)) return hipErrorInvalidValue;
         return launch_spmv_slab(*a.slab, a.vtype, MXE_SR_PLUS_TIMES, a.slab_off, a.slab_idx,
-                                a.slab_val, a.k, a.X, a.ldx, a.Y, a.ldy, s);
+                                a.slab_val, a.k, a.X, a.ldx, a.Y, a.ldy, win ? a.slab_wstart : nullptr,
+                                win ? a.slab_win : 0, s);
     }
     switch (a.vtype) {
     case VAL_F64: return spmv_t<double, double>(a, variant, s);

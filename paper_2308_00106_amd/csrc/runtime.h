@@ -30,6 +30,18 @@ mxe_status hip_fail(hipError_t e, const char *what);
         if (_e != hipSuccess) return ::mxe::hip_fail(_e, #call);        \
     } while (0)
 
+// Makes `dev` current for a scope and restores the previous device after it.
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) (void)hipSetDevice(dev);
+    }
+    ~DeviceGuard() {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
 struct Matrix {
     int64_t id = 0;
     int32_t nrows = 0, ncols = 0;
@@ -56,6 +68,10 @@ struct Matrix {
         int32_t *off = nullptr;
         uint32_t *idx = nullptr;
         void *val = nullptr;
+        // MXE_VAR_WINDOW on this layout (built on first use): per-block window
+        // starts and the window's rows of x
+        int32_t *wstart = nullptr;
+        int32_t win = 0;
     };
     // (k class, slab size in 64 KiB, CUs the geometry is sized for) -> layout
     std::map<std::tuple<int, int, int>, Slab> slabs;
@@ -82,7 +98,11 @@ struct TuneKey {
                std::tie(o.nrows, o.ncols, o.nnz, o.storage, o.kclass, o.seed, o.mode, o.root);
     }
 };
-struct TuneResult { int variant; int group_lanes; };
+struct TuneResult {
+    int variant;
+    int group_lanes;
+    bool forced = false;                // set by mxe_set_variant, not by the tuner
+};
 
 struct Plan {
     std::vector<mxe_item> items;
@@ -139,6 +159,7 @@ struct mxe_ctx {
     std::map<int64_t, std::unique_ptr<mxe::Plan>> plans;
     int64_t next_id = 1;
     int cu_count = 256;
+    size_t lds_per_cu = 0, lds_per_block = 0;   // bytes of LDS per CU / per workgroup
     mxe::Server *server = nullptr;      // owned; created and deleted by the serving loop
 };
 
@@ -153,6 +174,21 @@ mxe_status spmv_internal(mxe_ctx *ctx, Matrix &A, int32_t k, const void *X, int6
 mxe_status ensure_variant(mxe_ctx *ctx, Matrix &A, int32_t k, hipStream_t s, TuneResult *out);
 int elem_bytes_of(mxe_dtype d);
 uint64_t request_bytes(const Matrix &A, int32_t k);
+
+// Batches (api.cpp). One item's descriptor, before it is cut into pieces.
+// With `prepare`, tunes the item and builds the column-slab layout it runs on
+// when they do not exist yet (stream s); without it, only looks them up
+// (allocating nothing on the device) and fails with MXE_ERR_UNSUPPORTED for an
+// item that is not tuned yet. *lds grows to the dynamic LDS its block needs.
+mxe_status batch_item_desc(mxe_ctx *ctx, Matrix &A, const mxe_item &it, int32_t index,
+                           hipStream_t s, bool prepare, BatchDesc *out, size_t *lds);
+// Every item's descriptor (batch_item_desc), big items cut into pieces, and
+// the pieces dealt to the per-XCD queues.
+mxe_status build_batch_descs(mxe_ctx *ctx, int32_t count, const mxe_item *items, hipStream_t s,
+                             bool prepare, std::vector<BatchDesc> &descs,
+                             std::vector<int32_t> &qent, BatchQueues &qs, size_t *lds);
+// the value type every item shares, or -1 (the persistent kernel then carries every path)
+int batch_common_vtype(const std::vector<BatchDesc> &descs);
 
 // serving loop (serve.cpp)
 mxe_status serve_start(mxe_ctx *ctx, const mxe_serve_config *cfg);

@@ -37,16 +37,26 @@ template <> struct SlabVal<uint16_t, float> {
 // partial y (rows_per_block x KM values of T); soff: LDS for the wavefronts'
 // group offsets; vec_x: X rows are read as 16-byte vectors (slab_vec_x). The
 // caller separates two calls on one workgroup by a barrier.
-template <typename V, typename T, int KM, int SR>
+// WIN: X rows [w0, w0 + win) are first copied to LDS (xw, win x KM values of
+// T), and entries whose column falls there read x from LDS instead of
+// gathering it (the same values, so the same sums).
+template <typename V, typename T, int KM, int SR, bool WIN = false>
 __device__ __attribute__((always_inline)) inline void
 slab_block(const SlabGeom &g, int32_t block, int xcd, const int32_t *__restrict__ off,
            const uint32_t *__restrict__ idx, const V *__restrict__ val, int32_t k,
            const T *__restrict__ X, int64_t ldx, T *__restrict__ Y, int64_t ldy, int vec_x,
-           T *yp, int32_t (*soff)[kSlabMax + 1], int tid) {
+           T *yp, int32_t (*soff)[kSlabMax + 1], int tid, T *xw = nullptr, int32_t w0 = 0,
+           int32_t win = 0) {
     using S = Semiring<SR, T>;
     const int wave = tid / kWave, lane = tid % kWave;
     const int32_t R = g.rows_per_block;
     for (int i = tid; i < R * KM; i += kSlabBlock) yp[i] = S::identity();
+    if constexpr (WIN) {
+        for (int32_t i = tid; i < win * KM; i += kSlabBlock) {
+            const int32_t r = w0 + i / KM, q = i % KM;
+            xw[i] = (r < g.ncols && (KM == 1 || q < k)) ? X[(int64_t)r * ldx + q] : T(0);
+        }
+    }
     T *ywave = yp + (int64_t)wave * g.rows_per_sub * KM;
     // this wavefront's groups (one per slab) and their offsets
     const int32_t *o = off + ((int64_t)block * kSubBlocks + wave) * g.slabs;
@@ -76,6 +86,14 @@ slab_block(const SlabGeom &g, int32_t block, int xcd, const int32_t *__restrict_
 #pragma unroll
             for (int j = 0; j < kD; ++j) {
                 const bool v = u[j] != 0xffffffffu;
+                if constexpr (WIN) {
+                    const uint32_t d = (u[j] & cmask) - (uint32_t)w0;
+                    if (v && d < (uint32_t)win) {
+#pragma unroll
+                        for (int q = 0; q < KM; ++q) xv[j][q] = xw[(int64_t)d * KM + q];
+                        continue;
+                    }
+                }
                 const T *xr = X + (int64_t)(v ? (u[j] & cmask) : 0) * ldx;
                 if constexpr (KM > 1) {
                     if (vec_x) {                              // k == KM, 16-byte aligned rows

@@ -27,8 +27,10 @@ INPUT_DEVICE = OUTPUT_DEVICE = 0x1
 ROWS, COLS, GRADIENT = 0x1, 0x2, 0x4
 SPACE_PERMUTED, SPACE_ORIGINAL = 0x0, 0x1
 VAR_GROUP, VAR_BINNED, VAR_MERGE, VAR_SLAB, VAR_FIXED, VAR_COO = 0x000, 0x100, 0x200, 0x300, 0x400, 0x500
+VAR_WINDOW = 0x600                # SLAB layout plus an LDS window of x per row block
 SLAB_ONE_PER_CU = 0x80            # SLAB lanes flag: row blocks for one workgroup per CU
 SR_PLUS_TIMES, SR_MIN_PLUS, SR_OR_AND = 0, 1, 2
+SERVE_MAX_BATCH = 64              # requests per serving launch, at most
 
 
 def variant(family: int, lanes: int = 0) -> int:
@@ -57,7 +59,7 @@ class _Desc(ctypes.Structure):
 
 class _ServeCfg(ctypes.Structure):
     _fields_ = [("streams", ctypes.c_int32), ("max_inflight", ctypes.c_int32),
-                ("max_merge_k", ctypes.c_int32)]
+                ("max_batch", ctypes.c_int32)]
 
 
 _lib = None
@@ -406,8 +408,9 @@ class Context:
         _check(self._lib.mxe_batch_destroy(self._h, plan), "mxe_batch_destroy")
 
     # --- serving -------------------------------------------------------------------
-    def serve_start(self, streams: int = 4, max_inflight: int = 16, max_merge_k: int = 16) -> None:
-        cfg = _ServeCfg(streams, max_inflight, max_merge_k)
+    def serve_start(self, streams: int = 4, max_inflight: int = 32, max_batch: int = 8) -> None:
+        """max_batch: requests per persistent launch (1: each request its own product)."""
+        cfg = _ServeCfg(streams, max_inflight, max_batch)
         _check(self._lib.mxe_serve_start(self._h, ctypes.byref(cfg)), "mxe_serve_start")
 
     def submit(self, m: int, X, Y, flags: int = SPACE_PERMUTED) -> int:

@@ -260,13 +260,14 @@ def _alone_denominator(ref_csr, X, shape):
     return den.reshape(shape)
 
 
-def _serving_run(ctx, mats, handles, variants, merge_k, seed):
+def _serving_run(ctx, mats, handles, variants, max_batch, seed):
     """64 requests from two submitter threads on a few matrices (so requests
     on one matrix overlap on several streams), mixed k and index spaces; each
     result is compared with the same product run alone afterwards: bit for
-    bit when nothing is merged (merge_k 1: the same kernel on the same data),
-    else within the FP32 tolerance element by element, and against the
-    oracle either way."""
+    bit when every request runs as its own product (max_batch 1: the same
+    kernel on the same data), else within the FP32 tolerance element by
+    element (a batch runs an item on its own layout and work units), and
+    against the oracle either way."""
     rng = np.random.default_rng(seed)
     reqs = []
     for r in range(64):
@@ -278,7 +279,7 @@ def _serving_run(ctx, mats, handles, variants, merge_k, seed):
     for m, per_k in variants.items():
         for k, var in per_k.items():
             ctx.set_variant(handles[m], k, var)
-    ctx.serve_start(streams=4, max_inflight=16, max_merge_k=merge_k)
+    ctx.serve_start(streams=4, max_inflight=16, max_batch=max_batch)
     tickets = [None] * len(reqs)
 
     def submitter(lo, hi):
@@ -307,7 +308,7 @@ def _serving_run(ctx, mats, handles, variants, merge_k, seed):
             ref_csr = synth.CSR(A.nrows, A.ncols, *oracle.permute_csr(A, rperm, cperm))
         y_mix = Y.cpu().numpy().astype(np.float64)
         y_alone = Ya.cpu().numpy().astype(np.float64)
-        if merge_k == 1:
+        if max_batch == 1:
             assert np.array_equal(y_mix.view(np.uint64), y_alone.view(np.uint64)), (i, m, k, flags)
         else:
             den = _alone_denominator(ref_csr, X, y_mix.shape)
@@ -322,16 +323,18 @@ def _serving_run(ctx, mats, handles, variants, merge_k, seed):
 def test_serving_mix_matches_alone(ctx):
     """Concurrent requests on the same matrices, with the merge-path and COO
     kernels forced on two of them (their carries are per launch), agree with
-    the products run alone: bitwise unmerged, within tolerance merged."""
+    the products run alone: bitwise when each request is its own product,
+    within tolerance when rounds run as persistent batch launches."""
     mats = _pool(4, 300, rows=(20_000, 80_000))
     handles = [ctx.permute(ctx.register(A, "f32"), 5) for A in mats]
     merge = mx.variant(mx.VAR_MERGE)
     coo = mx.variant(mx.VAR_COO)
     variants = {0: {1: merge, 2: merge, 4: merge, 8: coo, 16: coo},
                 1: {1: coo, 2: coo, 4: coo, 8: coo, 16: coo}}
-    _serving_run(ctx, mats, handles, variants, merge_k=1, seed=1)
-    _serving_run(ctx, mats, handles, variants, merge_k=16, seed=2)
-    _serving_run(ctx, mats, handles, {}, merge_k=16, seed=3)
+    _serving_run(ctx, mats, handles, variants, max_batch=1, seed=1)
+    _serving_run(ctx, mats, handles, variants, max_batch=8, seed=2)
+    _serving_run(ctx, mats, handles, {}, max_batch=8, seed=3)
+    _serving_run(ctx, mats, handles, {}, max_batch=64, seed=4)
     for H in handles:
         ctx.release(H)
 
@@ -375,7 +378,7 @@ def test_serving_budget_admission_and_busy_release(ctx):
     # room for the matrix and one in-flight request: requests run one at a time
     with mx.Context(0, budget_bytes=resident + vec + 1024) as c2:
         H = c2.register(A0, "f32")
-        c2.serve_start(streams=2, max_inflight=8, max_merge_k=1)
+        c2.serve_start(streams=2, max_inflight=8, max_batch=1)
         X = synth.vector(A0.ncols, 3, k=8)
         Xd = torch_vec(X, torch.float32)
         Ys = [torch.empty((A0.nrows, 8), dtype=torch.float32, device="cuda") for _ in range(6)]
@@ -401,7 +404,7 @@ def test_serving_budget_admission_and_busy_release(ctx):
 def test_wait_timeout_and_unknown_ticket(ctx):
     A0 = synth.clustered_n2m(1, n=100_000)
     H = ctx.register(A0, "f32")
-    ctx.serve_start(streams=1, max_inflight=1, max_merge_k=1)
+    ctx.serve_start(streams=1, max_inflight=1, max_batch=1)
     X = torch_vec(synth.vector(A0.ncols, 3), torch.float32)
     Y = torch.empty(A0.nrows, dtype=torch.float32, device="cuda")
     t = ctx.submit(H, X, Y)

@@ -180,7 +180,11 @@ VARIANTS = [mx.variant(mx.VAR_GROUP, lanes) for lanes in (1, 2, 4, 8, 16, 32, 64
            [mx.variant(mx.VAR_BINNED), mx.variant(mx.VAR_MERGE),
             mx.variant(mx.VAR_SLAB, 1), mx.variant(mx.VAR_SLAB, 32),   # 64 KiB and 2 MiB slabs
             mx.variant(mx.VAR_SLAB, 16 | mx.SLAB_ONE_PER_CU),          # row blocks for one per CU
-            mx.variant(mx.VAR_FIXED, 4), mx.variant(mx.VAR_FIXED, 16), mx.variant(mx.VAR_COO)]
+            mx.variant(mx.VAR_FIXED, 4), mx.variant(mx.VAR_FIXED, 16), mx.variant(mx.VAR_COO),
+            # the slab layouts plus an LDS window of x per row block: one and two
+            # workgroups per CU, and 64 KiB slabs (many slabs around the window)
+            mx.variant(mx.VAR_WINDOW, 16 | mx.SLAB_ONE_PER_CU), mx.variant(mx.VAR_WINDOW, 32),
+            mx.variant(mx.VAR_WINDOW, 1)]
 
 
 def _force(ctx, H, k, v):
@@ -290,6 +294,40 @@ def test_every_variant_is_bitwise_repeatable(ctx, k):
     ctx.release(A)
 
 
+@pytest.mark.parametrize("storage", ["f64", "f32", "bf16"])
+@pytest.mark.parametrize("name", ["skewed", "wide", "clustered_n4096", "ragged"])
+def test_window_equals_slab_bitwise(ctx, storage, name):
+    """The window variant reads the same x values from LDS that the slab
+    variant gathers, on the same layout: the same sums, bit for bit, in both
+    the original (clustered) and the permuted matrix, for k classes 1 to 16."""
+    A0 = dict(CSR_CASES)[name]()
+    A = ctx.register(A0, storage)
+    B = ctx.permute(A, 3)
+    dt = torch.float64 if storage == "f64" else torch.float32
+    for H in (A, B):
+        for k in (1, 3, 8, 16):
+            X = torch_vec(synth.vector(A0.ncols, 5, k=k), dt)
+            outs = []
+            for fam in (mx.VAR_SLAB, mx.VAR_WINDOW):
+                for units in (16 | mx.SLAB_ONE_PER_CU, 4):
+                    if not _force(ctx, H, k, mx.variant(fam, units)):
+                        continue
+                    Y = torch.full((A0.nrows, k) if k > 1 else (A0.nrows,), float("nan"),
+                                   dtype=dt, device="cuda")
+                    ctx.spmv(H, X, Y)
+                    torch.cuda.synchronize()
+                    outs.append(((fam, units), Y.cpu().numpy().copy()))
+            by_units = {}
+            for (fam, units), Y in outs:
+                by_units.setdefault(units, []).append((fam, Y))
+            for units, ys in by_units.items():
+                if len(ys) == 2:
+                    assert np.array_equal(ys[0][1].view(np.uint8), ys[1][1].view(np.uint8)), \
+                        (name, storage, k, hex(units))
+    ctx.release(B)
+    ctx.release(A)
+
+
 def test_runs_are_bitwise_deterministic(ctx):
     A0 = synth.skewed_n4m(1, n=40_000)
     A = ctx.register(A0)
@@ -347,6 +385,14 @@ def test_full_size_clustered_n2m(ctx):
         ctx.spmv(B, xt, y)
         torch.cuda.synchronize()
         assert spmv_error(Bo, x, y.cpu().numpy(), "f64") <= 1e-13, hex(v)
+    # and every window layout the tuner may pick for the original matrix
+    for v in (mx.variant(mx.VAR_WINDOW, 16 | mx.SLAB_ONE_PER_CU),
+              mx.variant(mx.VAR_WINDOW, 32 | mx.SLAB_ONE_PER_CU), mx.variant(mx.VAR_WINDOW, 32)):
+        ctx.set_variant(A, 1, v)
+        y = torch.full((A0.nrows,), float("nan"), dtype=torch.float64, device="cuda")
+        ctx.spmv(A, xt, y)
+        torch.cuda.synchronize()
+        assert spmv_error(A0, x, y.cpu().numpy(), "f64") <= 1e-13, hex(v)
     ctx.release(B)
     ctx.release(A)
 
@@ -448,7 +494,7 @@ def test_tuning_keeps_only_the_chosen_slab_layout(ctx):
     v = ctx.tune(B, 1)
     delta = ctx.matrix_info(B).device_bytes - before
     layout = A0.nnz * 12                                  # uint32 word + FP64 value per entry
-    if (v & 0xf00) == mx.VAR_SLAB:
+    if (v & 0xf00) in (mx.VAR_SLAB, mx.VAR_WINDOW):
         assert layout <= delta < layout + 4 * (1 << 22), (hex(v), delta)
     else:
         assert delta == 0, (hex(v), delta)
