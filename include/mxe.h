@@ -313,6 +313,30 @@ mxe_status mxe_batch_create(mxe_ctx *ctx, int32_t count, const mxe_item *items, 
 mxe_status mxe_batch_launch(mxe_ctx *ctx, mxe_plan plan, const mxe_item *items, void *stream);
 mxe_status mxe_batch_destroy(mxe_ctx *ctx, mxe_plan plan);
 
+/* For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc. Computes
+ * what mxe_spmv_batch computes, with the same kernel, work units and queues
+ * (so the same bits), but allocates no device memory: the descriptor table,
+ * queue entries and queue counters live in a static device array of
+ * MXE_NOALLOC_SCRATCH_BYTES that the library keeps on every GPU it runs on
+ * until the process ends, which limits a call to MXE_NOALLOC_MAX_ITEMS items.
+ * Nothing is tuned or built here: every item's matrix must already be tuned
+ * for its k (MXE_ERR_UNSUPPORTED naming the item otherwise), and an item runs
+ * on the layout that an earlier mxe_spmv_batch or mxe_batch_create with the
+ * same matrix and k built; call one of them once with the same items first to
+ * get its result bit for bit. count above MXE_NOALLOC_MAX_ITEMS:
+ * MXE_ERR_INVALID_ARG. Stream-ordered on `stream`; the descriptor table is
+ * copied from host memory on that stream, and the call returns once the copy
+ * has taken its data. Every call on one GPU shares that GPU's array, which
+ * keeps the last call's contents (the counters are cleared by a kernel on
+ * `stream` before each use): calls whose work may overlap on one GPU (other
+ * streams, threads or contexts) race on it and must be ordered by the
+ * caller; calls on one stream are ordered already. */
+#define MXE_NOALLOC_MAX_ITEMS 256
+#define MXE_NOALLOC_SCRATCH_BYTES 65536
+mxe_status mxe_spmv_batch_noalloc(mxe_ctx *ctx, int32_t count, const mxe_item *items,
+                                  void *stream);
+
 /* --- serving: continuous batching of requests on resident matrices -------- */
 
 #define MXE_SERVE_MAX_BATCH 64

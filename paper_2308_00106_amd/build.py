@@ -17,7 +17,7 @@ BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libmxe.so")
 
 SOURCES = ["kernels_csr.hip", "kernels_entropy.hip", "kernels_spmv.hip", "kernels_slab.hip",
-           "kernels_batch.hip", "kernels_probe.hip", "api.cpp", "serve.cpp"]
+           "kernels_batch.hip", "kernels_probe.hip", "api.cpp", "serve.cpp", "batch_noalloc.cpp"]
 HEADERS = ["device_common.h", "internal.h", "runtime.h", "slab_device.h", "spmv_device.h"]
 
 ARCH = "gfx950"

@@ -615,6 +615,8 @@ mxe_status mxe_create(int32_t device, uint64_t hbm_budget_bytes, mxe_ctx **out) 
     MXE_HIP(hipDeviceGetDefaultMemPool(&pool, device));
     uint64_t thr = UINT64_MAX;
     MXE_HIP(hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr));
+    mxe_status st = noalloc_init(device);
+    if (st) return st;
     auto *ctx = new mxe_ctx();
     ctx->device = device;
     ctx->budget = hbm_budget_bytes;

@@ -190,6 +190,11 @@ mxe_status build_batch_descs(mxe_ctx *ctx, int32_t count, const mxe_item *items,
 // the value type every item shares, or -1 (the persistent kernel then carries every path)
 int batch_common_vtype(const std::vector<BatchDesc> &descs);
 
+// Allocation-free batches (batch_noalloc.cpp): looks up this device's copy of
+// the library's static scratch array once; called by mxe_create with the
+// device current.
+mxe_status noalloc_init(int device);
+
 // serving loop (serve.cpp)
 mxe_status serve_start(mxe_ctx *ctx, const mxe_serve_config *cfg);
 mxe_status serve_submit(mxe_ctx *ctx, const mxe_item *req, mxe_ticket *out);

@@ -30,6 +30,8 @@ VAR_GROUP, VAR_BINNED, VAR_MERGE, VAR_SLAB, VAR_FIXED, VAR_COO = 0x000, 0x100, 0
 VAR_WINDOW = 0x600                # SLAB layout plus an LDS window of x per row block
 SLAB_ONE_PER_CU = 0x80            # SLAB lanes flag: row blocks for one workgroup per CU
 SR_PLUS_TIMES, SR_MIN_PLUS, SR_OR_AND = 0, 1, 2
+# allocation-free batches: items per call, bytes of the static device scratch array
+NOALLOC_MAX_ITEMS, NOALLOC_SCRATCH_BYTES = 256, 65536
 SERVE_MAX_BATCH = 64              # requests per serving launch, at most
 
 
@@ -103,6 +105,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "mxe_probe_gather": ([P, i64, i64, i32, P, P], st),
         "mxe_spmv_semiring": ([P, i64, i32, i32, P, i64, P, i64, u32, P], st),
         "mxe_spmv_batch": ([P, i32, P, P], st),
+        "mxe_spmv_batch_noalloc": ([P, i32, P, P], st),
         "mxe_batch_create": ([P, i32, P, P], st),
         "mxe_batch_launch": ([P, i64, P, P], st),
         "mxe_batch_destroy": ([P, i64], st),
@@ -391,6 +394,13 @@ class Context:
         arr = self._items(items)
         _check(self._lib.mxe_spmv_batch(self._h, len(items), arr, _stream_ptr(stream)),
                "mxe_spmv_batch")
+
+    def spmv_batch_noalloc(self, items, stream=None) -> None:
+        """items: list of (matrix, X, Y), each matrix already prepared for its
+        k by spmv_batch or batch_create; allocates no device memory."""
+        arr = self._items(items)
+        _check(self._lib.mxe_spmv_batch_noalloc(self._h, len(items), arr, _stream_ptr(stream)),
+               "mxe_spmv_batch_noalloc")
 
     def batch_create(self, items) -> int:
         arr = self._items(items)
