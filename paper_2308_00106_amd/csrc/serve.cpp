@@ -22,6 +22,8 @@
 
 #include <algorithm>
 #include <chrono>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 
 #include "runtime.h"
@@ -85,6 +87,9 @@ struct Server {
     bool stop = false;
     int64_t next_ticket = 1;
     std::thread th;
+    // counters reported at serve_stop when MXE_LOG is set
+    int64_t n_rounds = 0, n_batched = 0, n_single = 0;
+    double issue_us = 0.0;
 
     void run();
     void retire_done();
@@ -246,11 +251,16 @@ bool Server::admit_round(std::unique_lock<std::mutex> &lk) {
     lk.unlock();
     mxe_status st;
     bool table = false;
+    const auto t_issue = Clock::now();
     {
         std::lock_guard<std::recursive_mutex> clk(ctx->mu);
         DeviceGuard g(ctx->device);
         st = issue(group, slot, &table);
     }
+    issue_us += std::chrono::duration<double, std::micro>(Clock::now() - t_issue).count();
+    ++n_rounds;
+    (table ? n_batched : n_single) += table ? (int64_t)nbatch : (int64_t)group.size();
+    if (table) n_single += (int64_t)(group.size() - nbatch);
     if (table) slot.table_busy = true;
     const bool recorded = st == MXE_OK && ev && hipEventRecord(ev, slot.s) == hipSuccess;
     lk.lock();
@@ -427,6 +437,10 @@ mxe_status serve_stop(mxe_ctx *ctx) {
     }
     srv->cv_work.notify_all();
     if (srv->th.joinable()) srv->th.join();
+    if (getenv("MXE_LOG") && srv->n_rounds)
+        fprintf(stderr, "[mxe] serving: %lld rounds, %lld requests batched, %lld single, %.1f us host issue per round\n",
+                (long long)srv->n_rounds, (long long)srv->n_batched, (long long)srv->n_single,
+                srv->issue_us / srv->n_rounds);
     DeviceGuard g(ctx->device);
     srv->free_slots();
     ctx->server = nullptr;
