@@ -266,7 +266,7 @@ def serving(ctx_unused, log, pool=32, warm=1000, n_req=20000, low_load_requests=
         standalone = {"gpu_p50_us": round(float(np.percentile(alone_gpu, 50)), 1),
                       "host_round_trip_p50_us": round(float(np.percentile(alone_host, 50)), 1),
                       "requests": len(alone_gpu)}
-        ctx.serve_start(streams=4, max_inflight=32, max_batch=8)
+        ctx.serve_start(streams=2, max_inflight=32, max_batch=8, max_merge_k=8)
 
         def run(rate, n_meas, n_warm, window=256):
             """rate None: closed loop (as fast as possible, at most `window`

@@ -343,22 +343,31 @@ mxe_status mxe_spmv_batch_noalloc(mxe_ctx *ctx, int32_t count, const mxe_item *i
 
 typedef struct mxe_serve_config {
     int32_t streams;            /* device streams the loop issues on (>= 1) */
-    int32_t max_inflight;       /* requests on the device at once (>= 1) */
-    int32_t max_batch;          /* requests per launch (1..MXE_SERVE_MAX_BATCH) */
+    int32_t max_inflight;       /* items (products) on the device at once (>= 1) */
+    int32_t max_batch;          /* items per launch (1..MXE_SERVE_MAX_BATCH) */
+    int32_t max_merge_k;        /* right-hand sides of a merged item (1..16; 1: no merging) */
 } mxe_serve_config;
 
-/* Starts the serving loop (one scheduler thread, `streams` device streams,
- * and per stream a device descriptor table with its pinned staging copy,
- * allocated here). Requests are admitted in arrival order while a slot is
- * free (max_inflight) and the in-flight vector bytes fit the context budget
+/* Starts the serving loop (one scheduler thread and `streams` device
+ * streams, each with a device descriptor table, its pinned twin and, when
+ * max_merge_k > 1, a staging matrix for merged right-hand sides: twice the
+ * widest resident matrix's columns times max_merge_k rounded up to a power of
+ * two, counted in the HBM budget; all allocated here). Requests are admitted
+ * in arrival order while the in-flight vector bytes fit the context budget
  * beside the resident matrices. Each admission round takes up to max_batch
- * queued requests: the permuted-space ones with k <= 16 become the items of
- * one persistent launch of mxe_spmv_batch's kernel (each request its own
- * item, nothing packed or copied), on the least-loaded stream whose table is
- * free; a round of one request, and original-space or k > 16 requests, run as
- * their own autotuned products (as mxe_spmv). With max_batch 1 every request
- * runs exactly as mxe_spmv would run it. Launches on different streams
- * overlap on the device. */
+ * items, each taking one of max_inflight slots: an item is one request, or
+ * queued permuted-space requests on the same matrix merged into one product
+ * of at most max_merge_k right-hand sides (the matrix streams once for all of
+ * them; their X are packed into the staging by one kernel per round and each
+ * result column is written into its own request's Y); a request merged into
+ * an item takes no slot of its own. A round of one
+ * unmerged request runs as its own autotuned product (as mxe_spmv);
+ * otherwise the permuted-space items run as one persistent launch of
+ * mxe_spmv_batch's kernel on the least-loaded stream whose table is free,
+ * and original-space or k > 16 requests as their own products. With
+ * max_batch 1 and max_merge_k 1 every request runs exactly as mxe_spmv would
+ * run it. Launches on different streams overlap on the device.
+ * MXE_ERR_BUDGET when the staging does not fit the budget. */
 mxe_status mxe_serve_start(mxe_ctx *ctx, const mxe_serve_config *cfg);
 /* Serving is Section 1's reuse as a service: matrices are permuted once and
  * stay resident; each request is one product Y = M X (Section 2; Eq. 1 when
@@ -367,8 +376,9 @@ mxe_status mxe_serve_start(mxe_ctx *ctx, const mxe_serve_config *cfg);
  * by the caller and must stay alive until mxe_wait returns for it; the
  * matrix's own creation, e.g. the stream given to mxe_permute, must be
  * complete). The first request on a matrix for a k class tunes the matrix
- * for it and builds the layout a batch runs it on, here in the submitting
- * thread, so the scheduler only looks them up. MXE_ERR_INVALID_ARG for a bad
+ * for it (and for each larger class a merge can reach) and builds the layouts
+ * a batch runs it on, here in the submitting thread, so the scheduler only
+ * looks them up. MXE_ERR_INVALID_ARG for a bad
  * request or no running loop, MXE_ERR_NOT_FOUND for an unknown matrix.
  * Thread-safe. */
 mxe_status mxe_submit(mxe_ctx *ctx, const mxe_item *req, mxe_ticket *out);

@@ -1234,23 +1234,75 @@ constexpr int kBatchSlabUnits = 16;
 // item whose variant was forced to a row family (mxe_set_variant) runs as row
 // tiles. lds: the dynamic LDS the launch needs (the largest slab block's
 // partial y).
+// The work unit a batch runs A's k-column products as (see build_batch_descs):
+// *r the tuning, *out the column-slab layout (null: row tiles). With `prepare`
+// it tunes and builds what is missing (stream s); without it, it only looks
+// them up. full: prefer the tuned layout, whose row blocks are sized for the
+// whole device, to the one sized for one XCD (for an item that is spread over
+// the XCDs: one cut into pieces, or one of a batch of few items).
+static mxe_status batch_layout(mxe_ctx *ctx, Matrix &A, int32_t k, int32_t index, hipStream_t s,
+                               bool prepare, bool full, TuneResult *r, const Matrix::Slab **out) {
+    mxe_status st;
+    *out = nullptr;
+    if (prepare) {
+        if ((st = ensure_variant(ctx, A, k, s, r))) return st;
+    } else {
+        auto tr = ctx->tuned.find(tune_key(A, k));
+        if (tr == ctx->tuned.end())
+            return fail(MXE_ERR_UNSUPPORTED, "batch item " + std::to_string(index) +
+                                                 " is not tuned for its k yet");
+        *r = tr->second;
+    }
+    const bool slab_tuned = slab_family(r->variant);
+    if (!slab_tuned && r->forced) return MXE_OK;                // row tiles
+    const int kc = kclass_of(k);
+    const int xcd_cus = std::max(1, ctx->cu_count / kBatchQueues);
+    const int units = slab_tuned ? slab_units_of(r->variant) : kBatchSlabUnits;
+    std::vector<int> cus{xcd_cus};
+    if (slab_tuned) {
+        cus.push_back(slab_cus_of(ctx, r->variant));
+        if (full) std::swap(cus[0], cus[1]);
+    }
+    const Matrix::Slab *sl = nullptr;
+    st = MXE_OK;
+    for (int c : cus) {
+        if (prepare) {
+            if ((st = ensure_slab(ctx, A, kc, units, c, s, &sl)) == MXE_OK) break;
+            sl = nullptr;
+        } else {
+            // the layout a preparing call would have picked, if it was built
+            auto f = A.slabs.find(std::make_tuple(kc, units, c));
+            if (f != A.slabs.end()) {
+                sl = &f->second;
+                break;
+            }
+        }
+    }
+    if (!sl && slab_tuned) {
+        if (prepare) return st;
+        return fail(MXE_ERR_UNSUPPORTED, "batch item " + std::to_string(index) +
+                                             " has no slab layout built yet");
+    }
+    *out = sl;
+    return MXE_OK;
+}
+
+mxe_status prepare_batch_layout(mxe_ctx *ctx, Matrix &A, int32_t k, hipStream_t s) {
+    TuneResult r;
+    const Matrix::Slab *sl;
+    return batch_layout(ctx, A, k, 0, s, true, false, &r, &sl);
+}
+
 mxe_status batch_item_desc(mxe_ctx *ctx, Matrix &A, const mxe_item &it, int32_t index,
-                           hipStream_t s, bool prepare, BatchDesc *out, size_t *lds) {
+                           hipStream_t s, bool prepare, bool full, BatchDesc *out, size_t *lds) {
     if (it.flags != MXE_SPACE_PERMUTED)
         return fail(MXE_ERR_UNSUPPORTED, "batches take permuted-space vectors only");
     if (it.k > 16) return fail(MXE_ERR_UNSUPPORTED, "batches take k <= 16");
     mxe_status st = check_dense(A, it.k, it.X, it.ldx, it.Y, it.ldy);
     if (st) return st;
     TuneResult r;
-    if (prepare) {
-        if ((st = ensure_variant(ctx, A, it.k, s, &r))) return st;
-    } else {
-        auto tr = ctx->tuned.find(tune_key(A, it.k));
-        if (tr == ctx->tuned.end())
-            return fail(MXE_ERR_UNSUPPORTED, "batch item " + std::to_string(index) +
-                                                 " is not tuned for its k yet");
-        r = tr->second;
-    }
+    const Matrix::Slab *sl;
+    if ((st = batch_layout(ctx, A, it.k, index, s, prepare, full, &r, &sl))) return st;
     BatchDesc d{};
     d.rp = A.rp;
     d.col = A.col;
@@ -1265,40 +1317,14 @@ mxe_status batch_item_desc(mxe_ctx *ctx, Matrix &A, const mxe_item &it, int32_t 
     d.kclass = kclass_of(it.k);
     d.lanes = std::max(r.group_lanes, d.kclass);   // set_variant may force fewer
     d.rows_per_tile = (kBatchBlock / d.lanes) * 2;
-    const bool slab_tuned = slab_family(r.variant);
-    if (slab_tuned || !r.forced) {
-        const int xcd_cus = std::max(1, ctx->cu_count / kBatchQueues);
-        const int units = slab_tuned ? slab_units_of(r.variant) : kBatchSlabUnits;
-        std::vector<int> cus{xcd_cus};
-        if (slab_tuned) cus.push_back(slab_cus_of(ctx, r.variant));
-        const Matrix::Slab *sl = nullptr;
-        for (int c : cus) {
-            if (prepare) {
-                if ((st = ensure_slab(ctx, A, d.kclass, units, c, s, &sl)) == MXE_OK) break;
-                sl = nullptr;
-            } else {
-                // the layout a preparing call would have picked, if it was built
-                auto f = A.slabs.find(std::make_tuple(d.kclass, units, c));
-                if (f != A.slabs.end()) {
-                    sl = &f->second;
-                    break;
-                }
-            }
-        }
-        if (!sl && slab_tuned) {
-            if (prepare) return st;
-            return fail(MXE_ERR_UNSUPPORTED, "batch item " + std::to_string(index) +
-                                                 " has no slab layout built yet");
-        }
-        if (sl) {
-            const int eb = elem_bytes_of(A.storage);
-            d.slab = sl->g;
-            d.slab_off = sl->off;
-            d.slab_idx = sl->idx;
-            d.slab_val = sl->val;
-            d.vec_x = slab_vec_x(d.kclass, it.k, it.X, it.ldx, eb) ? 1 : 0;
-            *lds = std::max(*lds, (size_t)sl->g.rows_per_block * d.kclass * eb);
-        }
+    if (sl) {
+        const int eb = elem_bytes_of(A.storage);
+        d.slab = sl->g;
+        d.slab_off = sl->off;
+        d.slab_idx = sl->idx;
+        d.slab_val = sl->val;
+        d.vec_x = slab_vec_x(d.kclass, it.k, it.X, it.ldx, eb) ? 1 : 0;
+        *lds = std::max(*lds, (size_t)sl->g.rows_per_block * d.kclass * eb);
     }
     d.unit0 = 0;
     d.units = (int32_t)item_units(d);
@@ -1309,22 +1335,36 @@ mxe_status batch_item_desc(mxe_ctx *ctx, Matrix &A, const mxe_item &it, int32_t 
 
 mxe_status build_batch_descs(mxe_ctx *ctx, int32_t count, const mxe_item *items, hipStream_t s,
                              bool prepare, std::vector<BatchDesc> &descs,
-                             std::vector<int32_t> &qent, BatchQueues &qs, size_t *lds) {
+                             std::vector<int32_t> &qent, BatchQueues &qs, size_t *lds, bool full) {
     if (count < 1 || !items) return fail(MXE_ERR_INVALID_ARG, "empty batch");
     descs.clear();
     *lds = 0;
+    std::vector<std::shared_ptr<Matrix>> mats;
     std::vector<uint64_t> cost;
-    int64_t tiles = 0;
+    uint64_t total = 0;
     for (int32_t i = 0; i < count; ++i) {
         auto A = find_matrix(ctx, items[i].mat);
         if (!A) return fail(MXE_ERR_NOT_FOUND, "unknown matrix handle in batch");
+        if (items[i].flags != MXE_SPACE_PERMUTED)
+            return fail(MXE_ERR_UNSUPPORTED, "batches take permuted-space vectors only");
+        if (items[i].k > 16) return fail(MXE_ERR_UNSUPPORTED, "batches take k <= 16");
+        mxe_status st = check_dense(*A, items[i].k, items[i].X, items[i].ldx, items[i].Y, items[i].ldy);
+        if (st) return st;
+        cost.push_back(request_bytes(*A, items[i].k));
+        total += cost.back();
+        mats.push_back(std::move(A));
+    }
+    int64_t tiles = 0;
+    for (int32_t i = 0; i < count; ++i) {
+        // an item that assign_queues will cut into pieces is spread over the
+        // XCDs anyway: it runs on the layout sized for the whole device
+        const bool spread = full || cost[i] * kBatchQueues > total;
         BatchDesc d;
-        mxe_status st = batch_item_desc(ctx, *A, items[i], i, s, prepare, &d, lds);
+        mxe_status st = batch_item_desc(ctx, *mats[i], items[i], i, s, prepare, spread, &d, lds);
         if (st) return st;
         tiles += d.units;
         if (tiles > INT32_MAX) return fail(MXE_ERR_UNSUPPORTED, "too many tiles in batch");
         descs.push_back(d);
-        cost.push_back(request_bytes(*A, items[i].k));
     }
     assign_queues(descs, cost, qent, qs);
     return MXE_OK;

@@ -118,8 +118,10 @@ hipError_t launch_slab_build(const SlabGeom &g, const int32_t *rp, const int32_t
 // values (elem_bytes each) on a 16-byte boundary: never a read past a row's k
 // values.
 inline bool slab_vec_x(int kclass, int32_t k, const void *X, int64_t ldx, int elem_bytes) {
-    return kclass > 1 && k == kclass && (ldx * elem_bytes) % 16 == 0 &&
-           (reinterpret_cast<uintptr_t>(X) % 16) == 0;
+    // the slab kernel reads an X row min(16, kclass x elem_bytes) bytes at a time
+    const int64_t vb = (int64_t)kclass * elem_bytes < 16 ? (int64_t)kclass * elem_bytes : 16;
+    return kclass > 1 && k == kclass && (ldx * elem_bytes) % vb == 0 &&
+           (reinterpret_cast<uintptr_t>(X) % vb) == 0;
 }
 // The x window of MXE_VAR_WINDOW: in a block's dynamic LDS, after its partial
 // y (rows_per_block x kclass values of elem_bytes), 16-byte aligned.
@@ -197,7 +199,12 @@ struct BatchDesc {             // one piece of one batch item (device-resident t
     int32_t tile_begin;        // first work unit of this piece within its queue
     int32_t unit0, units;      // the piece: the item's work units [unit0, unit0 + units)
     int32_t item;              // index of the item in the batch
-    int32_t vec_x;             // slab units: whole X rows as 16-byte loads (slab_vec_x)
+    // per-column outputs (null: column q goes to Y + q with ldy): column q of
+    // the result goes to ycol[q] (its row 0) with leading dimension ycol_ld[q],
+    // so one product can serve several requests' Y (device arrays of k)
+    void *const *ycol;
+    const int64_t *ycol_ld;
+    int32_t vec_x;             // slab units: whole X rows as vector loads (slab_vec_x)
     // slab units (slab_off non-null): one work unit per block of this layout
     // for k class kclass, in place of row tiles
     SlabGeom slab;
@@ -243,5 +250,17 @@ int64_t probe_gathers_issued(int64_t gathers, int32_t grid);
 // packed matrix (ldp); elem_bytes 8 or 4.
 hipError_t launch_copy_cols(int32_t n, int32_t k, const void *src, int64_t lds, void *dst,
                             int64_t ldd, int elem_bytes, hipStream_t s);
+// One column block of a packed matrix: rows [0, n) of src (k columns, leading
+// dimension lds) go to columns [c0, c0 + k) of dst (leading dimension ldd).
+struct PackCols {
+    const void *src;
+    int64_t lds;
+    void *dst;
+    int64_t ldd;
+    int32_t n, k, c0, pad;
+};
+// count entries of a device table, at once; max_n: the largest n among them.
+hipError_t launch_pack_cols(const PackCols *table, int32_t count, int32_t max_n, int elem_bytes,
+                            hipStream_t s);
 
 }  // namespace mxe

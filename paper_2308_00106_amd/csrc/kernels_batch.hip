@@ -22,6 +22,9 @@ static_assert(kBatchBlock == kSlabBlock, "slab units run one layout block per wo
 
 namespace {
 
+// bytes of x per lane each wavefront of a slab unit keeps in flight
+constexpr int kBatchInflight = 64;
+
 // Unit u of item d, which the host placed in queue q. A slab unit starts its
 // slab rotation at the one tied to q's XCD whichever workgroup runs it, so
 // every row's sum is taken in the same order on every launch.
@@ -40,8 +43,9 @@ batch_unit(const BatchDesc &d, int32_t u, int q, unsigned char *smem, int32_t (*
         const T *X = (const T *)d.X;
         T *Y = (T *)d.Y;
 #define MXE_BATCH_SLAB(KMV)                                                                        \
-    slab_block<V, T, KMV, 0>(d.slab, u, q, d.slab_off, d.slab_idx, sv, d.k, X, d.ldx, Y, d.ldy,  \
-                             d.vec_x, yp, soff, tid)
+    slab_block<V, T, KMV, 0, false, kBatchInflight>(d.slab, u, q, d.slab_off, d.slab_idx, sv, d.k,  \
+                                                   X, d.ldx, Y, d.ldy, d.vec_x, yp, soff, tid,    \
+                                                   nullptr, 0, 0, d.ycol, d.ycol_ld)
         switch (d.slab.kclass) {
         case 1: MXE_BATCH_SLAB(1); break;
         case 2: MXE_BATCH_SLAB(2); break;
@@ -54,14 +58,20 @@ batch_unit(const BatchDesc &d, int32_t u, int q, unsigned char *smem, int32_t (*
         const int32_t r0 = u * d.rows_per_tile;
         const int32_t r1 = min(d.nrows, r0 + d.rows_per_tile);
         rows_runtime<V, T, kBatchBlock>(d.rp, d.col, (const V *)d.val, d.k, (const T *)d.X, d.ldx,
-                                       (T *)d.Y, d.ldy, d.lanes, d.kclass, r0, r1, tid);
+                                       (T *)d.Y, d.ldy, d.lanes, d.kclass, r0, r1, tid, d.ycol,
+                                       d.ycol_ld);
     }
 }
 
 // VT is the value type shared by every item, or -1 for a batch that mixes
-// them (that instance carries every path and so more code).
+// them (that instance carries every path and so more code). The FP32-math
+// instances are held to two workgroups per CU (8 waves per SIMD): the
+// descriptor fields the compiler keeps in scalar registers would otherwise
+// take more than the 100 SGPRs that allows, and leave one workgroup per CU.
 template <int VT>
-__global__ __launch_bounds__(kBatchBlock) void k_spmv_batch(const BatchDesc *__restrict__ descs,
+__global__ __launch_bounds__(kBatchBlock)
+__attribute__((amdgpu_waves_per_eu(VT == VAL_F32 || VT == VAL_BF16 ? 8 : 1)))
+void k_spmv_batch(const BatchDesc *__restrict__ descs,
                                                            const int32_t *__restrict__ qent,
                                                            BatchQueues qs, int32_t *counters) {
     // slab units: the block's partial y (16-byte aligned for FP64 and vector LDS access)

@@ -413,6 +413,25 @@ __global__ __launch_bounds__(kBlock) void k_copy_cols(int32_t n, int32_t k, cons
         for (int32_t c = 0; c < k; ++c) dst[i * ldd + c] = src[i * lds + c];
 }
 
+// Several column blocks at once: entry blockIdx.y of the table copies its
+// source's k columns into columns [c0, c0 + k) of its destination, rows
+// [0, n); the grid's x dimension strides over the n x k elements, one per
+// thread in row-major order, so neighbouring threads touch neighbouring
+// addresses on both sides.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_pack_cols(const PackCols *__restrict__ table) {
+    const PackCols e = table[blockIdx.y];
+    const T *src = (const T *)e.src;
+    T *dst = (T *)e.dst + e.c0;
+    const int64_t total = (int64_t)e.n * e.k;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r = i / e.k;
+        const int32_t c = (int32_t)(i - r * e.k);
+        dst[r * e.ldd + c] = src[r * e.lds + c];
+    }
+}
+
 // ---- value conversion --------------------------------------------------------------
 
 __global__ __launch_bounds__(kBlock) void k_f64_to_f32(const double *in, float *out, int64_t n) {
@@ -716,6 +735,20 @@ hipError_t launch_copy_cols(int32_t n, int32_t k, const void *src, int64_t lds, 
     else if (elem_bytes == 4)
         hipLaunchKernelGGL(k_copy_cols<float>, dim3(g), dim3(kBlock), 0, s, n, k,
                            (const float *)src, lds, (float *)dst, ldd);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_pack_cols(const PackCols *table, int32_t count, int32_t max_n, int elem_bytes,
+                            hipStream_t s) {
+    if (count <= 0 || max_n <= 0) return hipSuccess;
+    // max_n rows of up to 16 columns per entry
+    const dim3 grid(grid_for((int64_t)max_n * 16, kBlock, 2048), count);
+    if (elem_bytes == 8)
+        hipLaunchKernelGGL(k_pack_cols<double>, grid, dim3(kBlock), 0, s, table);
+    else if (elem_bytes == 4)
+        hipLaunchKernelGGL(k_pack_cols<float>, grid, dim3(kBlock), 0, s, table);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();

@@ -180,13 +180,19 @@ uint64_t request_bytes(const Matrix &A, int32_t k);
 // when they do not exist yet (stream s); without it, only looks them up
 // (allocating nothing on the device) and fails with MXE_ERR_UNSUPPORTED for an
 // item that is not tuned yet. *lds grows to the dynamic LDS its block needs.
+// full: prefer each item's tuned layout (row blocks sized for the whole
+// device) to the one sized for one XCD, for batches of few items.
 mxe_status batch_item_desc(mxe_ctx *ctx, Matrix &A, const mxe_item &it, int32_t index,
-                           hipStream_t s, bool prepare, BatchDesc *out, size_t *lds);
+                           hipStream_t s, bool prepare, bool full, BatchDesc *out, size_t *lds);
 // Every item's descriptor (batch_item_desc), big items cut into pieces, and
 // the pieces dealt to the per-XCD queues.
 mxe_status build_batch_descs(mxe_ctx *ctx, int32_t count, const mxe_item *items, hipStream_t s,
                              bool prepare, std::vector<BatchDesc> &descs,
-                             std::vector<int32_t> &qent, BatchQueues &qs, size_t *lds);
+                             std::vector<int32_t> &qent, BatchQueues &qs, size_t *lds,
+                             bool full = false);
+// Tunes A for k and builds the layouts a batch item of k columns may run on
+// (as batch_item_desc with prepare), without an item.
+mxe_status prepare_batch_layout(mxe_ctx *ctx, Matrix &A, int32_t k, hipStream_t s);
 // the value type every item shares, or -1 (the persistent kernel then carries every path)
 int batch_common_vtype(const std::vector<BatchDesc> &descs);
 

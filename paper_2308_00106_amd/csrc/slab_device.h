@@ -12,9 +12,14 @@ namespace mxe {
 constexpr int kSlabBlock = 1024;                    // 16 wavefronts
 constexpr int kSubBlocks = kSlabBlock / kWave;      // wavefront sub-blocks per block
 constexpr int kSlabMax = 64;                        // column slabs per layout
-// 64-entry chunks each wavefront keeps in flight (fewer for wide right-hand sides)
-template <int KM> struct SlabUnroll { static constexpr int value = KM <= 2 ? 4 : KM <= 4 ? 2 : 1; };
-
+// 64-entry chunks each wavefront keeps in flight. IF = 0 (the single-product
+// kernels): four for one or two right-hand sides, two for four, one above.
+// IF > 0 (the persistent batch kernel): as many as keep about IF bytes of x
+// per lane in flight, 1 to 8.
+template <int KM, typename T, int IF> struct SlabUnroll {
+    static constexpr int B = IF / (KM * (int)sizeof(T));
+    static constexpr int value = IF == 0 ? (KM <= 2 ? 4 : KM <= 4 ? 2 : 1) : B < 1 ? 1 : B > 8 ? 8 : B;
+};
 template <typename V, typename T> struct SlabVal;
 template <> struct SlabVal<double, double> {
     __device__ static double get(double v) { return v; }
@@ -31,22 +36,25 @@ template <> struct SlabVal<uint16_t, float> {
 // starts at the slab tied to XCD `xcd` (its own XCD; in a batch, the XCD of
 // the queue the block came from), all together (a barrier after each slab),
 // so its wavefronts gather from the same L2-resident x slice; inside a slab a
-// wavefront loads up to SlabUnroll chunks of its group at once, issues their x
+// wavefront loads up to SlabUnroll<KM, T, IF> chunks of its group at once, issues their x
 // gathers together, then reduces each chunk by row. The first batch of the
 // next slab's group is loaded before each barrier. yp: LDS for the block's
 // partial y (rows_per_block x KM values of T); soff: LDS for the wavefronts'
-// group offsets; vec_x: X rows are read as 16-byte vectors (slab_vec_x). The
+// group offsets; vec_x: X rows are read as vectors of min(16, KM x sizeof(T))
+// bytes (slab_vec_x). The
 // caller separates two calls on one workgroup by a barrier.
 // WIN: X rows [w0, w0 + win) are first copied to LDS (xw, win x KM values of
 // T), and entries whose column falls there read x from LDS instead of
 // gathering it (the same values, so the same sums).
-template <typename V, typename T, int KM, int SR, bool WIN = false>
+// ycol (may be null): column q of the result goes to ycol[q] (its row 0)
+// with leading dimension ycol_ld[q] instead of Y + q with ldy.
+template <typename V, typename T, int KM, int SR, bool WIN = false, int IF = 0>
 __device__ __attribute__((always_inline)) inline void
 slab_block(const SlabGeom &g, int32_t block, int xcd, const int32_t *__restrict__ off,
            const uint32_t *__restrict__ idx, const V *__restrict__ val, int32_t k,
            const T *__restrict__ X, int64_t ldx, T *__restrict__ Y, int64_t ldy, int vec_x,
            T *yp, int32_t (*soff)[kSlabMax + 1], int tid, T *xw = nullptr, int32_t w0 = 0,
-           int32_t win = 0) {
+           int32_t win = 0, void *const *ycol = nullptr, const int64_t *ycol_ld = nullptr) {
     using S = Semiring<SR, T>;
     const int wave = tid / kWave, lane = tid % kWave;
     const int32_t R = g.rows_per_block;
@@ -64,7 +72,7 @@ slab_block(const SlabGeom &g, int32_t block, int xcd, const int32_t *__restrict_
     __syncthreads();
     const int s0 = (int)(((int64_t)xcd * g.slabs) / 8);
     const uint32_t cmask = (1u << g.cbits) - 1u;
-    constexpr int kD = SlabUnroll<KM>::value;
+    constexpr int kD = SlabUnroll<KM, T, IF>::value;
     uint32_t u[kD];
     T a[kD];
     auto load_batch = [&](int32_t c, int32_t e) {             // up to kD chunks of [c, e)
@@ -96,7 +104,7 @@ slab_block(const SlabGeom &g, int32_t block, int xcd, const int32_t *__restrict_
                 }
                 const T *xr = X + (int64_t)(v ? (u[j] & cmask) : 0) * ldx;
                 if constexpr (KM > 1) {
-                    if (vec_x) {                              // k == KM, 16-byte aligned rows
+                    if (vec_x) {                              // k == KM, rows aligned to the vector
                         constexpr int W = (16 / (int)sizeof(T)) < KM ? 16 / (int)sizeof(T) : KM;
                         typedef T vec_t __attribute__((ext_vector_type(W)));
 #pragma unroll
@@ -143,7 +151,10 @@ slab_block(const SlabGeom &g, int32_t block, int xcd, const int32_t *__restrict_
     for (int i = tid; i < R * KM; i += kSlabBlock) {
         const int64_t row = row0 + i / KM;
         const int q = i % KM;
-        if (row < g.nrows && (KM == 1 || q < k)) Y[row * ldy + q] = yp[i];
+        if (row < g.nrows && (KM == 1 || q < k)) {
+            if (ycol) static_cast<T *>(ycol[q])[row * ycol_ld[q]] = yp[i];
+            else Y[row * ldy + q] = yp[i];
+        }
     }
 }
 

@@ -29,11 +29,14 @@ template <> struct ValLoad<uint16_t, float> {
 // a time, KM column lanes times L / KM entry lanes, then an xor butterfly over
 // the entry lanes. One code path for every (L, KM) keeps a single accumulator
 // in registers. Groups are L-aligned, so the shuffles stay inside a group.
+// ycol (may be null): column q of the result goes to ycol[q] (its row 0) with
+// leading dimension ycol_ld[q] instead of Y + q with ldy.
 template <typename V, typename T, int NT>
 __device__ inline void rows_runtime(const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
                                     const V *__restrict__ val, int32_t k, const T *__restrict__ X,
                                     int64_t ldx, T *__restrict__ Y, int64_t ldy, int L, int KM,
-                                    int32_t r0, int32_t r1, int tid) {
+                                    int32_t r0, int32_t r1, int tid, void *const *ycol = nullptr,
+                                    const int64_t *ycol_ld = nullptr) {
     const int E = L / KM;
     const int lane = tid % L, q = lane % KM, el = lane / KM;
     const bool active = q < k;
@@ -55,7 +58,10 @@ __device__ inline void rows_runtime(const int32_t *__restrict__ rp, const int32_
             acc += a0 * (active ? X[(int64_t)c0 * ldx + q] : T(0));
         }
         for (int off = L / 2; off >= KM; off >>= 1) acc += __shfl_xor(acc, off);
-        if (el == 0 && active) Y[(int64_t)row * ldy + q] = acc;
+        if (el == 0 && active) {
+            if (ycol) static_cast<T *>(ycol[q])[(int64_t)row * ycol_ld[q]] = acc;
+            else Y[(int64_t)row * ldy + q] = acc;
+        }
     }
 }
 

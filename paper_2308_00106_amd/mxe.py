@@ -61,7 +61,7 @@ class _Desc(ctypes.Structure):
 
 class _ServeCfg(ctypes.Structure):
     _fields_ = [("streams", ctypes.c_int32), ("max_inflight", ctypes.c_int32),
-                ("max_batch", ctypes.c_int32)]
+                ("max_batch", ctypes.c_int32), ("max_merge_k", ctypes.c_int32)]
 
 
 _lib = None
@@ -418,9 +418,12 @@ class Context:
         _check(self._lib.mxe_batch_destroy(self._h, plan), "mxe_batch_destroy")
 
     # --- serving -------------------------------------------------------------------
-    def serve_start(self, streams: int = 4, max_inflight: int = 32, max_batch: int = 8) -> None:
-        """max_batch: requests per persistent launch (1: each request its own product)."""
-        cfg = _ServeCfg(streams, max_inflight, max_batch)
+    def serve_start(self, streams: int = 2, max_inflight: int = 32, max_batch: int = 8,
+                    max_merge_k: int = 8) -> None:
+        """max_inflight: products on the device at once; max_batch: items per
+        persistent launch; max_merge_k: right-hand sides of a merged item (1
+        and 1: each request its own product)."""
+        cfg = _ServeCfg(streams, max_inflight, max_batch, max_merge_k)
         _check(self._lib.mxe_serve_start(self._h, ctypes.byref(cfg)), "mxe_serve_start")
 
     def submit(self, m: int, X, Y, flags: int = SPACE_PERMUTED) -> int:

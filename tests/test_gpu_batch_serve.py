@@ -182,9 +182,11 @@ def test_batch_slab_units(ctx):
 
 
 def test_batch_slab_layout_within_budget():
-    """A batch gives a slab-tuned item a second layout with row blocks sized
-    for one XCD; when the HBM budget has no room for it the item runs on its
-    tuned layout, with a correct result either way."""
+    """A batch gives a slab-tuned item that stays on one XCD (here eight equal
+    items, none above an eighth of the batch) a second layout with row blocks
+    sized for one XCD; when the HBM budget has no room for it the items run on
+    their tuned layout, with a correct result either way. An item alone in a
+    batch is spread over every XCD and runs on its tuned layout."""
     A0 = synth.clustered_n2m(1, n=200_000)
     k = 4
     X = synth.vector(A0.ncols, 6, k=k)
@@ -201,16 +203,20 @@ def test_batch_slab_layout_within_budget():
         Bo = synth.CSR(A0.nrows, A0.ncols, *oracle.permute_csr(A0, rperm, cperm))
         return A, H, Xd, Bo
 
-    def run_batch(c, H, Xd, Bo):
-        Y = torch.full((A0.nrows, k), float("nan"), dtype=torch.float32, device="cuda")
-        c.spmv_batch([(H, Xd, Y)])
+    def run_batch(c, H, Xd, Bo, n=8):
+        Ys = [torch.full((A0.nrows, k), float("nan"), dtype=torch.float32, device="cuda")
+              for _ in range(n)]
+        c.spmv_batch([(H, Xd, Y) for Y in Ys])
         torch.cuda.synchronize()
-        assert spmv_error(Bo, X, Y.cpu().numpy().astype(np.float64), "f32") <= TOL["f32"]
+        for Y in Ys:
+            assert spmv_error(Bo, X, Y.cpu().numpy().astype(np.float64), "f32") <= TOL["f32"]
 
     with mx.Context(0) as c1:
         A, H, Xd, Bo = setup(c1)
         resident = c1.matrix_info(A).device_bytes + c1.matrix_info(H).device_bytes
         before = c1.matrix_info(H).device_bytes
+        run_batch(c1, H, Xd, Bo, n=1)
+        assert c1.matrix_info(H).device_bytes == before   # spread: the tuned layout ran
         run_batch(c1, H, Xd, Bo)
         grown = c1.matrix_info(H).device_bytes - before
         assert grown >= A0.nnz * 8                        # the per-XCD layout was built
@@ -260,14 +266,16 @@ def _alone_denominator(ref_csr, X, shape):
     return den.reshape(shape)
 
 
-def _serving_run(ctx, mats, handles, variants, max_batch, seed):
+def _serving_run(ctx, mats, handles, variants, max_batch, seed, max_merge_k=1, storage="f32"):
     """64 requests from two submitter threads on a few matrices (so requests
     on one matrix overlap on several streams), mixed k and index spaces; each
     result is compared with the same product run alone afterwards: bit for
-    bit when every request runs as its own product (max_batch 1: the same
-    kernel on the same data), else within the FP32 tolerance element by
-    element (a batch runs an item on its own layout and work units), and
-    against the oracle either way."""
+    bit when every request runs as its own product (max_batch and max_merge_k
+    1: the same kernel on the same data), else within the tolerance element
+    by element (a batch runs an item on its own layout and work units, a
+    merged item sums its columns in another order), and against the oracle
+    either way."""
+    dt = torch.float64 if storage == "f64" else torch.float32
     rng = np.random.default_rng(seed)
     reqs = []
     for r in range(64):
@@ -275,11 +283,13 @@ def _serving_run(ctx, mats, handles, variants, max_batch, seed):
         k = int(rng.integers(1, 9))
         flags = mx.SPACE_ORIGINAL if r % 3 == 0 else mx.SPACE_PERMUTED
         X = _rand_x(mats[m], k, seed * 1000 + r)
-        reqs.append((m, k, flags, X, torch_vec(X, torch.float32), _empty_y(mats[m], k)))
+        Y = torch.full((mats[m].nrows, k) if k > 1 else (mats[m].nrows,), float("nan"), dtype=dt,
+                       device="cuda")
+        reqs.append((m, k, flags, X, torch_vec(X, dt), Y))
     for m, per_k in variants.items():
         for k, var in per_k.items():
             ctx.set_variant(handles[m], k, var)
-    ctx.serve_start(streams=4, max_inflight=16, max_batch=max_batch)
+    ctx.serve_start(streams=4, max_inflight=16, max_batch=max_batch, max_merge_k=max_merge_k)
     tickets = [None] * len(reqs)
 
     def submitter(lo, hi):
@@ -297,7 +307,7 @@ def _serving_run(ctx, mats, handles, variants, max_batch, seed):
     assert all(v > 0 for v in lat)
     perms = {m: ctx.get_permutation(h) for m, h in enumerate(handles)}
     for i, (m, k, flags, X, Xd, Y) in enumerate(reqs):
-        Ya = _empty_y(mats[m], k)
+        Ya = torch.full_like(Y, float("nan"))
         ctx.spmv(handles[m], Xd, Ya, flags=flags)
         torch.cuda.synchronize()
         A = mats[m]
@@ -308,13 +318,13 @@ def _serving_run(ctx, mats, handles, variants, max_batch, seed):
             ref_csr = synth.CSR(A.nrows, A.ncols, *oracle.permute_csr(A, rperm, cperm))
         y_mix = Y.cpu().numpy().astype(np.float64)
         y_alone = Ya.cpu().numpy().astype(np.float64)
-        if max_batch == 1:
+        if max_batch == 1 and max_merge_k == 1:
             assert np.array_equal(y_mix.view(np.uint64), y_alone.view(np.uint64)), (i, m, k, flags)
         else:
             den = _alone_denominator(ref_csr, X, y_mix.shape)
             d = np.abs(y_mix - y_alone)
-            assert np.all(d <= TOL["f32"] * np.where(den == 0, 1, den)), (i, m, k, flags)
-        assert spmv_error(ref_csr, X, y_mix, "f32") <= TOL["f32"], (i, m, k, flags)
+            assert np.all(d <= TOL[storage] * np.where(den == 0, 1, den)), (i, m, k, flags)
+        assert spmv_error(ref_csr, X, y_mix, storage) <= TOL[storage], (i, m, k, flags)
     for m, per_k in variants.items():
         for k in per_k:
             ctx.set_variant(handles[m], k, 0)
@@ -333,8 +343,15 @@ def test_serving_mix_matches_alone(ctx):
                 1: {1: coo, 2: coo, 4: coo, 8: coo, 16: coo}}
     _serving_run(ctx, mats, handles, variants, max_batch=1, seed=1)
     _serving_run(ctx, mats, handles, variants, max_batch=8, seed=2)
-    _serving_run(ctx, mats, handles, {}, max_batch=8, seed=3)
-    _serving_run(ctx, mats, handles, {}, max_batch=64, seed=4)
+    _serving_run(ctx, mats, handles, variants, max_batch=8, seed=3, max_merge_k=16)
+    _serving_run(ctx, mats, handles, {}, max_batch=8, seed=4, max_merge_k=16)
+    _serving_run(ctx, mats, handles, {}, max_batch=64, seed=5, max_merge_k=7)
+    _serving_run(ctx, mats, handles, {}, max_batch=1, seed=6, max_merge_k=16)
+    for H in handles:
+        ctx.release(H)
+    # FP64 storage: merged right-hand sides packed as 8-byte values
+    handles = [ctx.permute(ctx.register(A, "f64"), 5) for A in mats]
+    _serving_run(ctx, mats, handles, {}, max_batch=8, seed=7, max_merge_k=16, storage="f64")
     for H in handles:
         ctx.release(H)
 
@@ -378,7 +395,7 @@ def test_serving_budget_admission_and_busy_release(ctx):
     # room for the matrix and one in-flight request: requests run one at a time
     with mx.Context(0, budget_bytes=resident + vec + 1024) as c2:
         H = c2.register(A0, "f32")
-        c2.serve_start(streams=2, max_inflight=8, max_batch=1)
+        c2.serve_start(streams=2, max_inflight=8, max_batch=1, max_merge_k=1)
         X = synth.vector(A0.ncols, 3, k=8)
         Xd = torch_vec(X, torch.float32)
         Ys = [torch.empty((A0.nrows, 8), dtype=torch.float32, device="cuda") for _ in range(6)]
@@ -404,7 +421,7 @@ def test_serving_budget_admission_and_busy_release(ctx):
 def test_wait_timeout_and_unknown_ticket(ctx):
     A0 = synth.clustered_n2m(1, n=100_000)
     H = ctx.register(A0, "f32")
-    ctx.serve_start(streams=1, max_inflight=1, max_batch=1)
+    ctx.serve_start(streams=1, max_inflight=1, max_batch=1, max_merge_k=1)
     X = torch_vec(synth.vector(A0.ncols, 3), torch.float32)
     Y = torch.empty(A0.nrows, dtype=torch.float32, device="cuda")
     t = ctx.submit(H, X, Y)

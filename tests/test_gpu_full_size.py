@@ -98,8 +98,9 @@ def test_batch_full_size(ctx):
 def test_serving_full_size(ctx):
     """The serving loop on full-size pool matrices (block-clustered and skewed,
     up to 1.76M rows, FP32) in the benchmark's configuration (4 streams, 32 in
-    flight, rounds of up to 8 requests per launch): 48 requests of k = 1..8
-    submitted at once, every output checked against the FP64 oracle."""
+    flight, rounds of up to 8 items per launch, requests on one matrix merged
+    up to k = 16): 48 requests of k = 1..8 submitted at once, every output
+    checked against the FP64 oracle."""
     pool = [synth.serving_member(i) for i in (0, 1, 2, 3, 5)]
     print("serving pool rows", [A.nrows for A in pool], flush=True)
     hs = [ctx.permute(ctx.register(A, "f32"), 1000 + i) for i, A in enumerate(pool)]
@@ -116,7 +117,7 @@ def test_serving_full_size(ctx):
         Y = torch.full((pool[m].nrows, k) if k > 1 else (pool[m].nrows,), float("nan"),
                        dtype=torch.float32, device="cuda")
         reqs.append((m, X, torch_vec(X, torch.float32), Y))
-    ctx.serve_start(streams=4, max_inflight=32, max_batch=8)
+    ctx.serve_start(streams=2, max_inflight=32, max_batch=8, max_merge_k=8)
     tickets = [ctx.submit(hs[m], Xd, Y) for m, _, Xd, Y in reqs]
     for t in tickets:
         ctx.wait(t)
