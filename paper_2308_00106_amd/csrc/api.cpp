@@ -1222,15 +1222,19 @@ static void assign_queues(std::vector<BatchDesc> &descs, std::vector<uint64_t> &
     qs.qbegin[kBatchQueues] = (int32_t)qent.size();
 }
 
-// slab size (in 64 KiB of x) of the batch layout for an item not tuned to the slab kernel
-constexpr int kBatchSlabUnits = 16;
+// largest slab (in 64 KiB of x) of a batch layout sized for one XCD, and the
+// slab of an item not tuned to the slab kernel: with two workgroups per CU an
+// XCD works on parts of two or three items at once, and larger slabs of each
+// no longer stay together in its L2
+constexpr int kBatchSlabUnits = 8;
 
 // One desc per item (before pieces), each item's work unit chosen by the
 // batch itself: the blocks of a column-slab layout whose row blocks are sized
 // for one XCD's CUs (the item's x is gathered by one XCD) with the tuned slab
-// size, or 1 MiB of x for an item tuned to a row kernel; a slab-tuned item
-// falls back to its tuned layout, any other to row tiles of its tuned GROUP
-// lane count, when that layout does not fit the matrix or the HBM budget. An
+// size up to kBatchSlabUnits, or kBatchSlabUnits for an item tuned to a row
+// kernel; a slab-tuned item falls back to its tuned layout, any other to row
+// tiles of its tuned GROUP lane count, when that layout does not fit the
+// matrix or the HBM budget. An
 // item whose variant was forced to a row family (mxe_set_variant) runs as row
 // tiles. lds: the dynamic LDS the launch needs (the largest slab block's
 // partial y).
@@ -1266,12 +1270,15 @@ static mxe_status batch_layout(mxe_ctx *ctx, Matrix &A, int32_t k, int32_t index
     const Matrix::Slab *sl = nullptr;
     st = MXE_OK;
     for (int c : cus) {
+        // the tuned layout keeps its slabs; one for an XCD takes at most kBatchSlabUnits
+        const int u = (slab_tuned && c == slab_cus_of(ctx, r->variant)) ? units
+                                                                        : std::min(units, kBatchSlabUnits);
         if (prepare) {
-            if ((st = ensure_slab(ctx, A, kc, units, c, s, &sl)) == MXE_OK) break;
+            if ((st = ensure_slab(ctx, A, kc, u, c, s, &sl)) == MXE_OK) break;
             sl = nullptr;
         } else {
             // the layout a preparing call would have picked, if it was built
-            auto f = A.slabs.find(std::make_tuple(kc, units, c));
+            auto f = A.slabs.find(std::make_tuple(kc, u, c));
             if (f != A.slabs.end()) {
                 sl = &f->second;
                 break;
