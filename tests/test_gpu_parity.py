@@ -229,7 +229,7 @@ def test_spmv_all_variants_f64(ctx, name, make, k):
 @pytest.mark.parametrize("name,make", CSR_CASES[:4] + CSR_CASES[5:])
 def test_spmv_reduced_precision(ctx, storage, name, make):
     A0 = make()
-    for k in (1, 4, 8, 12, 16):
+    for k in (1, 2, 4, 8, 12, 16):
         X = synth.vector(A0.ncols, 2, k=k)
         A = ctx.register(A0, storage)
         Xt = torch_vec(X, torch.float32)
@@ -244,6 +244,40 @@ def test_spmv_reduced_precision(ctx, storage, name, make):
             err = spmv_error(A0, X, Yh, storage)           # vs FP64 oracle, original values
             assert err <= TOL[storage], (name, storage, k, hex(v), err)
         ctx.release(A)
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "bf16"])
+def test_slab_x_rows_vector_or_scalar(ctx, storage):
+    """The slab kernel reads an X row as vectors of min(16, k x 4 or 8) bytes
+    only when k fills its class and the rows are aligned to that width, else
+    element by element: both ways, on the permuted and the original matrix,
+    for leading dimensions k (aligned), k + 1 and k + 2 (aligned or not)."""
+    import torch
+    A0 = synth.clustered_n4096(1)
+    A = ctx.register(A0, storage)
+    B = ctx.permute(A, 9)
+    rperm, cperm = ctx.get_permutation(B)
+    Bo = synth.CSR(A0.nrows, A0.ncols, *oracle.permute_csr(A0, rperm, cperm))
+    dt = torch.float64 if storage == "f64" else torch.float32
+    tol = TOL["f64"] if storage == "f64" else TOL["f32"]     # against the stored values
+    for H, Ho in ((A, A0), (B, Bo)):
+        for k in (2, 4, 8):
+            for v in (mx.variant(mx.VAR_SLAB, 16), mx.variant(mx.VAR_WINDOW, 32)):
+                if not _force(ctx, H, k, v):
+                    continue
+                for ld in (k, k + 1, k + 2):
+                    X = synth.vector(A0.ncols, 20 + ld, k=k)
+                    Xf = X.astype(np.float32).astype(np.float64) if storage != "f64" else X
+                    Xs = torch.zeros((A0.ncols, ld), dtype=dt, device="cuda")
+                    Xs[:, :k] = torch_vec(Xf, dt)
+                    Y = torch.full((A0.nrows, k), float("nan"), dtype=dt, device="cuda")
+                    ctx.spmv(H, Xs[:, :k], Y)
+                    torch.cuda.synchronize()
+                    err = spmv_error(Ho, Xf, Y.cpu().numpy().astype(np.float64), storage,
+                                     ref_stored=True)
+                    assert err <= tol, (storage, k, ld, hex(v), err)
+    ctx.release(B)
+    ctx.release(A)
 
 
 def test_identity_original_space(ctx):
