@@ -240,6 +240,27 @@ static int slab_cus_of(const mxe_ctx *ctx, int variant) {
     return (variant & MXE_SLAB_ONE_PER_CU) ? std::max(1, ctx->cu_count / 2) : ctx->cu_count;
 }
 
+// LDS a slab layout gives a block's partial y: half the CU's LDS, so two
+// workgroups of any layout fit on a CU (the batch kernel runs two per CU),
+// less 8 KiB for the kernels' own arrays and the allocation granule.
+static int64_t slab_y_lds(const mxe_ctx *ctx) {
+    return std::min<int64_t>((int64_t)ctx->lds_per_cu / 2, (int64_t)ctx->lds_per_block) - 8 * 1024;
+}
+
+// Blocks of a single product's layout that run at once: two per CU of the
+// device. A batch's per-XCD layouts (sized for one XCD's CUs) feed work
+// queues instead, where the largest blocks are best: 0.
+static int64_t slab_resident(const mxe_ctx *ctx, int cus) {
+    const int xcd_cus = std::max(1, ctx->cu_count / kBatchQueues);
+    return cus == xcd_cus ? 0 : 2 * (int64_t)ctx->cu_count;
+}
+
+static bool layout_geometry(const mxe_ctx *ctx, const Matrix &A, int kclass, int units, int cus,
+                            SlabGeom *g) {
+    return slab_geometry(A.nrows, A.ncols, kclass, vtype_of(A.storage), cus, slab_bytes_of(units),
+                         slab_y_lds(ctx), slab_resident(ctx, cus), g);
+}
+
 // cus: the compute units whose workgroups share the matrix, which sizes the
 // row blocks (all of the device for a single product, one XCD's in a batch)
 static mxe_status ensure_slab(mxe_ctx *ctx, Matrix &A, int kclass, int units, int cus,
@@ -251,8 +272,7 @@ static mxe_status ensure_slab(mxe_ctx *ctx, Matrix &A, int kclass, int units, in
         return MXE_OK;
     }
     Matrix::Slab sl;
-    if (!slab_geometry(A.nrows, A.ncols, kclass, vtype_of(A.storage), cus, slab_bytes_of(units),
-                       &sl.g))
+    if (!layout_geometry(ctx, A, kclass, units, cus, &sl.g))
         return fail(MXE_ERR_UNSUPPORTED, "column-slab layout does not fit this matrix");
     const int vb = val_bytes_of(A.storage);
     const size_t noff = slab_offsets_count(sl.g);
@@ -375,8 +395,7 @@ static mxe_status tune(mxe_ctx *ctx, Matrix &A, int32_t k, hipStream_t s, TuneRe
                       24 | MXE_SLAB_ONE_PER_CU}) {
         const int v = MXE_VARIANT(MXE_VAR_SLAB, units);
         SlabGeom g;
-        if (slab_geometry(A.nrows, A.ncols, kc, vtype_of(A.storage), slab_cus_of(ctx, v),
-                          slab_bytes_of(slab_units_of(v)), &g))
+        if (layout_geometry(ctx, A, kc, slab_units_of(v), slab_cus_of(ctx, v), &g))
             cands.push_back(v);
     }
     // the same layouts with an LDS window of x per row block (one workgroup
@@ -384,8 +403,7 @@ static mxe_status tune(mxe_ctx *ctx, Matrix &A, int32_t k, hipStream_t s, TuneRe
     for (int units : {16 | MXE_SLAB_ONE_PER_CU, 32 | MXE_SLAB_ONE_PER_CU, 32}) {
         const int v = MXE_VARIANT(MXE_VAR_WINDOW, units);
         SlabGeom g;
-        if (slab_geometry(A.nrows, A.ncols, kc, vtype_of(A.storage), slab_cus_of(ctx, v),
-                          slab_bytes_of(slab_units_of(v)), &g) &&
+        if (layout_geometry(ctx, A, kc, slab_units_of(v), slab_cus_of(ctx, v), &g) &&
             window_rows(ctx, g, (int)eb) > 0)
             cands.push_back(v);
     }
@@ -1134,8 +1152,7 @@ mxe_status mxe_set_variant(mxe_ctx *ctx, mxe_mat m, int32_t k, int32_t variant) 
         const int units = slab_units_of(variant);
         if (units < 1 || units > 64)
             return fail(MXE_ERR_INVALID_ARG, "slab size must be 1..64 x 64 KiB");
-        if (!slab_geometry(A->nrows, A->ncols, kclass_of(k), vtype_of(A->storage),
-                           slab_cus_of(ctx, variant), slab_bytes_of(units), &sg))
+        if (!layout_geometry(ctx, *A, kclass_of(k), units, slab_cus_of(ctx, variant), &sg))
             return fail(MXE_ERR_UNSUPPORTED, "column-slab layout does not fit this matrix");
         if (family == MXE_VAR_WINDOW && window_rows(ctx, sg, elem_bytes_of(A->storage)) < 1)
             return fail(MXE_ERR_UNSUPPORTED, "no LDS left for an x window in this layout");
@@ -1269,10 +1286,15 @@ static mxe_status batch_layout(mxe_ctx *ctx, Matrix &A, int32_t k, int32_t index
     }
     const Matrix::Slab *sl = nullptr;
     st = MXE_OK;
+    // a layout for one XCD takes slabs of at most kBatchSlabUnits, or the
+    // fewest 64 KiB more that keep it within 64 slabs
+    const int64_t x_bytes = (int64_t)A.ncols * kc * elem_bytes_of(A.storage);
+    const int min_units = (int)std::min<int64_t>(64, (x_bytes + 64 * 65536 - 1) / (64 * 65536));
     for (int c : cus) {
-        // the tuned layout keeps its slabs; one for an XCD takes at most kBatchSlabUnits
-        const int u = (slab_tuned && c == slab_cus_of(ctx, r->variant)) ? units
-                                                                        : std::min(units, kBatchSlabUnits);
+        // the tuned layout keeps its slabs
+        const int u = (slab_tuned && c == slab_cus_of(ctx, r->variant))
+                          ? units
+                          : std::max(std::min(units, kBatchSlabUnits), min_units);
         if (prepare) {
             if ((st = ensure_slab(ctx, A, kc, u, c, s, &sl)) == MXE_OK) break;
             sl = nullptr;

@@ -106,9 +106,14 @@ struct SlabGeom {
     int32_t rows_per_block, rows_per_sub; // workgroup block, wavefront sub-block
     int32_t blocks, kclass;
 };
-// false when the matrix cannot use the layout (packed indices would not fit)
+// cu_count: the CUs the row blocks are sized for (two blocks each);
+// y_lds_bytes: the LDS a block's partial y may take; resident: the blocks
+// that run at once, in whose whole waves rows are spread when y_lds_bytes
+// caps the blocks (0: blocks of the capped size, for the batch's work
+// queues). false when the matrix cannot use the layout (packed indices would
+// not fit)
 bool slab_geometry(int32_t nrows, int32_t ncols, int kclass, int vtype, int cu_count,
-                   int64_t slab_bytes, SlabGeom *g);
+                   int64_t slab_bytes, int64_t y_lds_bytes, int64_t resident, SlabGeom *g);
 size_t slab_offsets_count(const SlabGeom &g);
 size_t slab_build_ws_bytes(const SlabGeom &g);
 hipError_t launch_slab_build(const SlabGeom &g, const int32_t *rp, const int32_t *col,

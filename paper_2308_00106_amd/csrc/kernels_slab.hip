@@ -283,7 +283,7 @@ __global__ __launch_bounds__(kSlabBlock) void k_slab_window(SlabGeom g, const in
 }  // namespace
 
 bool slab_geometry(int32_t nrows, int32_t ncols, int kclass, int vtype, int cu_count,
-                   int64_t slab_bytes, SlabGeom *g) {
+                   int64_t slab_bytes, int64_t y_lds_bytes, int64_t resident, SlabGeom *g) {
     if (nrows <= 0 || ncols <= 0) return false;
     const int64_t xb = vtype == VAL_F64 ? 8 : 4;
     const int64_t per_col = xb * kclass;
@@ -291,9 +291,23 @@ bool slab_geometry(int32_t nrows, int32_t ncols, int kclass, int vtype, int cu_c
     if (slabs > kSlabMax) return false;
     const int64_t width = cdiv(ncols, slabs);
     slabs = cdiv(ncols, width);
-    // rows per block: two blocks per CU cover the matrix if LDS allows (64 KB each)
-    const int64_t lds_rows = (64 * 1024) / per_col;
-    int64_t R = std::min<int64_t>(cdiv(nrows, 2 * (int64_t)cu_count), lds_rows);
+    // rows per block: two blocks per CU cover the matrix if the block's
+    // partial y fits y_lds_bytes of LDS; else, with resident > 0, the rows are
+    // spread evenly over as many whole waves of the `resident` blocks that run
+    // at once as that takes, so no wave runs with only a few blocks (with
+    // resident 0, blocks of the largest size, for a work queue)
+    // (at most 16384 rows: the build's row-start table stays within 64 KiB of LDS)
+    const int64_t lds_rows = std::max<int64_t>(
+        kSubBlocks, std::min<int64_t>(16384, y_lds_bytes / per_col) / kSubBlocks * kSubBlocks);
+    int64_t R = cdiv(nrows, 2 * (int64_t)cu_count);
+    if (R > lds_rows) {
+        if (resident > 0) {
+            const int64_t waves = cdiv(nrows, resident * lds_rows);
+            R = cdiv(nrows, waves * resident);
+        } else {
+            R = lds_rows;
+        }
+    }
     R = std::max<int64_t>(R, kSubBlocks);
     R = cdiv(R, kSubBlocks) * kSubBlocks;
     // packed words (row in sub-block, global column) stay below 2^31, so they
