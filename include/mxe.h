@@ -352,7 +352,7 @@ typedef struct mxe_serve_config {
  * streams, each with a device descriptor table, its pinned twin and, when
  * max_merge_k > 1, a staging matrix for merged right-hand sides: twice the
  * widest resident matrix's columns times max_merge_k rounded up to a power of
- * two, counted in the HBM budget; all allocated here). Requests are admitted
+ * two, at least 64 MiB, counted in the HBM budget; all allocated here). Requests are admitted
  * in arrival order while the in-flight vector bytes fit the context budget
  * beside the resident matrices. Each admission round takes up to max_batch
  * items, each taking one of max_inflight slots: an item is one request, or
