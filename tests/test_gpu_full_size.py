@@ -127,3 +127,35 @@ def test_serving_full_size(ctx):
         assert err <= TOL["f32"], (i, m, err)
     for H in hs:
         ctx.release(H)
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_slab_blocks_spread_over_whole_waves(ctx, storage):
+    """Wide right-hand sides on a large matrix, where a row block's partial y
+    no longer fits the LDS that two blocks per CU allow: the slab layout then
+    spreads the rows over whole waves of the resident blocks. 700,000 rows,
+    k = 8 and 16, the 2 MiB column-slab variants at one and two workgroups
+    per CU forced, on the original and the permuted matrix, every output
+    element against the oracle on the stored values."""
+    A0 = synth.block_clustered(700_000, 8, 4096, 0.9, 21)
+    print(f"wide-k n={A0.nrows} nnz={A0.nnz} {storage}", flush=True)
+    A = ctx.register(A0, storage)
+    B = ctx.permute(A, 4)
+    rperm, cperm = ctx.get_permutation(B)
+    Bo = synth.CSR(A0.nrows, A0.ncols, *oracle.permute_csr(A0, rperm, cperm))
+    dt = torch.float64 if storage == "f64" else torch.float32
+    tol = TOL["f64"] if storage == "f64" else TOL["f32"]
+    for H, Ho in ((A, A0), (B, Bo)):
+        for k in (8, 16):
+            X = synth.vector(A0.ncols, 30 + k, k=k)
+            Xf = X if storage == "f64" else X.astype(np.float32).astype(np.float64)
+            Xd = torch_vec(Xf, dt)
+            for v in (mx.variant(mx.VAR_SLAB, 32), mx.variant(mx.VAR_SLAB, 32 | mx.SLAB_ONE_PER_CU)):
+                ctx.set_variant(H, k, v)
+                Y = torch.full((A0.nrows, k), float("nan"), dtype=dt, device="cuda")
+                ctx.spmv(H, Xd, Y)
+                torch.cuda.synchronize()
+                err = spmv_error(Ho, Xf, Y.cpu().numpy().astype(np.float64), storage, ref_stored=True)
+                assert err <= tol, (storage, k, hex(v), err)
+    ctx.release(B)
+    ctx.release(A)
