@@ -366,7 +366,11 @@ typedef struct mxe_serve_config {
  * mxe_spmv_batch's kernel on the least-loaded stream whose table is free,
  * and original-space or k > 16 requests as their own products. With
  * max_batch 1 and max_merge_k 1 every request runs exactly as mxe_spmv would
- * run it. Launches on different streams overlap on the device.
+ * run it. Launches on different streams overlap on the device. The
+ * scheduler thread polls without sleeping while products run and for 2 ms
+ * after the last one ends (a woken thread would add tens of microseconds to
+ * a lone request), then sleeps until the next submission: it keeps one host
+ * core busy under load.
  * MXE_ERR_BUDGET when the staging does not fit the budget. */
 mxe_status mxe_serve_start(mxe_ctx *ctx, const mxe_serve_config *cfg);
 /* Serving is Section 1's reuse as a service: matrices are permuted once and
