@@ -339,7 +339,12 @@ def serving(ctx_unused, log, pool=32, warm=1000, n_req=20000, low_load_requests=
             log(f"serving poisson {frac}: {r}")
         low = run(0.05 * rmax, low_load_requests, low_load_requests // 10)
         low["offered_req_per_s"] = round(0.05 * rmax, 1)
+        # a served latency runs from submission to the loop seeing the
+        # completion, so it holds a launch and a completion check: the host
+        # round trip is its like-for-like standalone figure, the GPU time the
+        # floor
         low["p50_over_standalone_gpu_p50"] = round(low["p50_us"] / standalone["gpu_p50_us"], 3)
+        low["p50_over_standalone_host_p50"] = round(low["p50_us"] / standalone["host_round_trip_p50_us"], 3)
         out["poisson_0.05"] = low
         log(f"serving poisson 0.05: {low}")
         ctx.serve_stop()
