@@ -391,6 +391,9 @@ bool Server::admit_round(std::unique_lock<std::mutex> &lk) {
     for (Item &it : round) (it.reqs.size() > 1 ? n_merged : n_single) += (int64_t)it.reqs.size();
     if (table) slot.table_busy = true;
     const bool recorded = st == MXE_OK && ev && hipEventRecord(ev, slot.s) == hipSuccess;
+    // untracked, what did launch may still read the stream's table and
+    // staging: let it end before the next round may rewrite them
+    if (!recorded && table) (void)hipStreamSynchronize(slot.s);
     lk.lock();
     if (recorded) {
         Launch l;
