@@ -150,10 +150,11 @@ mxe_status mxe_matrix_info(mxe_ctx *ctx, mxe_mat m, mxe_matrix_desc *out);
 /* Releases a handle. A permuted matrix keeps its parent's memory until it is
  * released too, and a batch plan keeps its matrices' memory until the plan is
  * destroyed. Returns MXE_ERR_BUSY while serving work on it is queued or
- * running. When the last reference to a matrix's memory goes, the call waits
- * for the work that library calls queued on that matrix (on each stream they
- * used, up to its last such call) before the memory is freed; it does not
- * wait for the rest of the device. */
+ * running. When the last reference to a matrix's memory goes, the memory is
+ * freed in stream order behind the work that library calls queued on that
+ * matrix (on each stream they used, up to its last such call), on a stream
+ * the context owns; the call returns without waiting for that work or for
+ * the rest of the device, and the handle is invalid at once. */
 mxe_status mxe_release(mxe_ctx *ctx, mxe_mat m);
 
 /* --- measure (Sections 4 and 5) --------------------------------------------- */

@@ -91,18 +91,41 @@ mxe_status reserve(mxe_ctx *ctx, uint64_t bytes) {
     }
 }
 
-// When the last reference goes, the work each stream queued on the matrix
-// (its last recorded use) finishes before the memory returns to the pool;
-// other streams and unrelated work are not waited for.
+// Destroys the retired use events that have fired (all of them with `all`,
+// once the device is idle).
+static void sweep_retired(mxe_ctx *ctx, bool all) {
+    std::lock_guard<std::mutex> lk(ctx->retired_mu);
+    auto &v = ctx->retired;
+    for (size_t i = 0; i < v.size();) {
+        if (all || hipEventQuery(v[i]) == hipSuccess) {
+            (void)hipEventDestroy(v[i]);
+            v[i] = v.back();
+            v.pop_back();
+        } else {
+            ++i;
+        }
+    }
+}
+
+// When the last reference goes, the memory returns to the pool in stream
+// order on the context's free stream, behind the work each stream queued on
+// the matrix (its last recorded use); the host waits for nothing. Should a
+// wait fail to queue, the host waits for those uses instead.
 std::shared_ptr<Matrix> make_matrix(mxe_ctx *ctx) {
     int dev = ctx->device;
     return std::shared_ptr<Matrix>(new Matrix(), [ctx, dev](Matrix *m) {
         DeviceGuard g(dev);
-        for (const Matrix::Use &u : m->uses) {
-            (void)hipEventSynchronize(u.ev);
-            (void)hipEventDestroy(u.ev);
+        sweep_retired(ctx, false);
+        bool ordered = ctx->free_stream != nullptr;
+        for (const Matrix::Use &u : m->uses)
+            if (ordered && hipStreamWaitEvent(ctx->free_stream, u.ev, 0) != hipSuccess) ordered = false;
+        if (!ordered)
+            for (const Matrix::Use &u : m->uses) (void)hipEventSynchronize(u.ev);
+        {
+            std::lock_guard<std::mutex> lk(ctx->retired_mu);
+            for (const Matrix::Use &u : m->uses) ctx->retired.push_back(u.ev);
         }
-        for (void *p : m->allocs) (void)hipFreeAsync(p, nullptr);
+        for (void *p : m->allocs) (void)hipFreeAsync(p, ordered ? ctx->free_stream : nullptr);
         ctx->used -= m->bytes;
         delete m;
     });
@@ -637,6 +660,10 @@ mxe_status mxe_create(int32_t device, uint64_t hbm_budget_bytes, mxe_ctx **out) 
     if (st) return st;
     auto *ctx = new mxe_ctx();
     ctx->device = device;
+    if (hipStreamCreateWithFlags(&ctx->free_stream, hipStreamNonBlocking) != hipSuccess) {  // default priority
+        delete ctx;
+        return fail(MXE_ERR_DEVICE, "stream creation failed");
+    }
     ctx->budget = hbm_budget_bytes;
     ctx->cu_count = prop.multiProcessorCount;
     ctx->lds_per_cu = prop.maxSharedMemoryPerMultiProcessor;
@@ -654,6 +681,9 @@ mxe_status mxe_destroy(mxe_ctx *ctx) {
         (void)hipDeviceSynchronize();
         ctx->plans.clear();
         ctx->mats.clear();
+        (void)hipStreamSynchronize(ctx->free_stream);
+        sweep_retired(ctx, true);
+        (void)hipStreamDestroy(ctx->free_stream);
     }
     delete ctx;
     return MXE_OK;

@@ -78,7 +78,7 @@ struct Matrix {
     std::atomic<int> busy{0};           // serving requests queued or running
     std::vector<void *> allocs;         // device allocations to free
     // per stream, an event recorded after the last work queued there on this
-    // matrix: freeing waits for these, never for the whole device
+    // matrix: its memory is freed behind these, never behind the whole device
     struct Use {
         hipStream_t s;
         hipEvent_t ev;
@@ -161,6 +161,13 @@ struct mxe_ctx {
     int cu_count = 256;
     size_t lds_per_cu = 0, lds_per_block = 0;   // bytes of LDS per CU / per workgroup
     mxe::Server *server = nullptr;      // owned; created and deleted by the serving loop
+    // A released matrix's memory is freed on this stream, after it has waited
+    // for the last use of the matrix on every stream, so releasing never
+    // blocks the host. The use events it waited on are destroyed once they
+    // have fired (or when the context goes).
+    hipStream_t free_stream = nullptr;
+    std::mutex retired_mu;
+    std::vector<hipEvent_t> retired;
 };
 
 namespace mxe {

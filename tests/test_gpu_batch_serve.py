@@ -386,6 +386,42 @@ def test_carry_variants_on_two_streams(ctx, family):
     ctx.release(A)
 
 
+def test_release_frees_behind_queued_products(ctx):
+    """A matrix released while products on it are still queued on a side
+    stream is freed behind them, in stream order: they still read intact
+    memory, and a matrix registered, permuted and multiplied right after on
+    the default stream (its memory may come from the freed blocks) is exact."""
+    A0 = synth.clustered_n2m(3, n=400_000)
+    A = ctx.register(A0, "f64")
+    B = ctx.permute(A, 11)
+    X = torch_vec(np.random.default_rng(2).uniform(-1, 1, A0.ncols), torch.float64)
+    ref = torch.empty(A0.nrows, dtype=torch.float64, device="cuda")
+    ctx.spmv(B, X, ref)
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream()
+    outs = [torch.full((A0.nrows,), float("nan"), dtype=torch.float64, device="cuda")
+            for _ in range(12)]
+    torch.cuda.synchronize()
+    for Y in outs:
+        ctx.spmv(B, X, Y, stream=side)
+    ctx.release(B)
+    ctx.release(A)
+    A1 = synth.clustered_n2m(4, n=400_000)
+    C = ctx.register(A1, "f64")
+    D = ctx.permute(C, 12)
+    Z = torch.empty(A1.nrows, dtype=torch.float64, device="cuda")
+    ctx.spmv(D, X, Z)
+    torch.cuda.synchronize()
+    for i, Y in enumerate(outs):
+        assert torch.equal(Y, ref), i
+    rperm, cperm = ctx.get_permutation(D)
+    Dp = synth.CSR(A1.nrows, A1.ncols, *oracle.permute_csr(A1, rperm, cperm))
+    err = spmv_error(Dp, X.cpu().numpy(), Z.cpu().numpy(), "f64")
+    assert err <= TOL["f64"], err
+    ctx.release(D)
+    ctx.release(C)
+
+
 def test_serving_budget_admission_and_busy_release(ctx):
     A0 = synth.clustered_n2m(1, n=200_000)
     with mx.Context(0, budget_bytes=0) as probe:
