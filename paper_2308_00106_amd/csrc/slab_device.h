@@ -74,14 +74,17 @@ slab_block(const SlabGeom &g, int32_t block, int xcd, const int32_t *__restrict_
     const uint32_t cmask = (1u << g.cbits) - 1u;
     constexpr int kD = SlabUnroll<KM, T, IF>::value;
     uint32_t u[kD];
-    T a[kD];
+    // values as stored, widened where they are used: widening BF16 here, in
+    // the branch that loads it, made each chunk wait for its value before the
+    // next chunk's loads went out
+    V a[kD];
     auto load_batch = [&](int32_t c, int32_t e) {             // up to kD chunks of [c, e)
 #pragma unroll
         for (int j = 0; j < kD; ++j) {
             const int32_t p = c + j * kWave + lane;
             const bool v = p < e;
             u[j] = v ? idx[p] : 0xffffffffu;
-            a[j] = v ? SlabVal<V, T>::get(val[p]) : T(0);
+            a[j] = v ? val[p] : V{};
         }
     };
     load_batch(soff[wave][s0], soff[wave][s0 + 1]);
@@ -124,9 +127,10 @@ slab_block(const SlabGeom &g, int32_t block, int xcd, const int32_t *__restrict_
                 if (c + j * kWave >= e) break;                // uniform per wavefront
                 // padding lanes (key 0xffffffff) sit after every valid lane
                 const uint32_t key = u[j] != 0xffffffffu ? (u[j] >> g.cbits) : 0xffffffffu;
+                const T aj = SlabVal<V, T>::get(a[j]);
                 T prod[KM];
 #pragma unroll
-                for (int q = 0; q < KM; ++q) prod[q] = S::mul(a[j], xv[j][q]);
+                for (int q = 0; q < KM; ++q) prod[q] = S::mul(aj, xv[j][q]);
                 if constexpr (SR == 0) segmented_scan<T, KM>(key, prod);
                 else segmented_scan_op<S, T, KM>(key, prod);
                 const uint32_t nxt = __shfl_down(key, 1);
