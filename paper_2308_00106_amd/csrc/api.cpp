@@ -91,43 +91,44 @@ mxe_status reserve(mxe_ctx *ctx, uint64_t bytes) {
     }
 }
 
-// Destroys the retired use events that have fired (all of them with `all`,
-// once the device is idle).
-static void sweep_retired(mxe_ctx *ctx, bool all) {
-    std::lock_guard<std::mutex> lk(ctx->retired_mu);
-    auto &v = ctx->retired;
+// Frees the memory of released matrices whose last uses have all finished
+// (all of them with `all`, once the device is idle).
+static void reap_pending(mxe_ctx *ctx, bool all) {
+    std::lock_guard<std::mutex> lk(ctx->pending_mu);
+    auto &v = ctx->pending;
     for (size_t i = 0; i < v.size();) {
-        if (all || hipEventQuery(v[i]) == hipSuccess) {
-            (void)hipEventDestroy(v[i]);
-            v[i] = v.back();
-            v.pop_back();
-        } else {
+        bool done = true;
+        for (hipEvent_t e : v[i].evs)
+            if (!all && hipEventQuery(e) == hipErrorNotReady) done = false;
+        if (!done) {
             ++i;
+            continue;
         }
+        for (hipEvent_t e : v[i].evs) (void)hipEventDestroy(e);
+        for (void *p : v[i].ptrs) (void)hipFreeAsync(p, nullptr);
+        v[i] = std::move(v.back());
+        v.pop_back();
     }
 }
 
-// When the last reference goes, the memory returns to the pool in stream
-// order on the context's free stream, behind the work each stream queued on
-// the matrix (its last recorded use); the host waits for nothing. Should a
-// wait fail to queue, the host waits for those uses instead.
+// When the last reference goes, the memory returns to the pool at once if
+// the work each stream queued on the matrix (its last recorded use) has
+// finished, else at a later library call that finds it finished; the host
+// waits for nothing and unrelated work is never waited for.
 std::shared_ptr<Matrix> make_matrix(mxe_ctx *ctx) {
     int dev = ctx->device;
     return std::shared_ptr<Matrix>(new Matrix(), [ctx, dev](Matrix *m) {
         DeviceGuard g(dev);
-        sweep_retired(ctx, false);
-        bool ordered = ctx->free_stream != nullptr;
-        for (const Matrix::Use &u : m->uses)
-            if (ordered && hipStreamWaitEvent(ctx->free_stream, u.ev, 0) != hipSuccess) ordered = false;
-        if (!ordered)
-            for (const Matrix::Use &u : m->uses) (void)hipEventSynchronize(u.ev);
+        mxe_ctx::PendingFree pf;
+        for (const Matrix::Use &u : m->uses) pf.evs.push_back(u.ev);
+        pf.ptrs = std::move(m->allocs);
         {
-            std::lock_guard<std::mutex> lk(ctx->retired_mu);
-            for (const Matrix::Use &u : m->uses) ctx->retired.push_back(u.ev);
+            std::lock_guard<std::mutex> lk(ctx->pending_mu);
+            ctx->pending.push_back(std::move(pf));
         }
-        for (void *p : m->allocs) (void)hipFreeAsync(p, ordered ? ctx->free_stream : nullptr);
         ctx->used -= m->bytes;
         delete m;
+        reap_pending(ctx, false);
     });
 }
 
@@ -660,10 +661,6 @@ mxe_status mxe_create(int32_t device, uint64_t hbm_budget_bytes, mxe_ctx **out) 
     if (st) return st;
     auto *ctx = new mxe_ctx();
     ctx->device = device;
-    if (hipStreamCreateWithFlags(&ctx->free_stream, hipStreamNonBlocking) != hipSuccess) {  // default priority
-        delete ctx;
-        return fail(MXE_ERR_DEVICE, "stream creation failed");
-    }
     ctx->budget = hbm_budget_bytes;
     ctx->cu_count = prop.multiProcessorCount;
     ctx->lds_per_cu = prop.maxSharedMemoryPerMultiProcessor;
@@ -681,9 +678,8 @@ mxe_status mxe_destroy(mxe_ctx *ctx) {
         (void)hipDeviceSynchronize();
         ctx->plans.clear();
         ctx->mats.clear();
-        (void)hipStreamSynchronize(ctx->free_stream);
-        sweep_retired(ctx, true);
-        (void)hipStreamDestroy(ctx->free_stream);
+        (void)hipDeviceSynchronize();
+        reap_pending(ctx, true);
     }
     delete ctx;
     return MXE_OK;
@@ -701,6 +697,7 @@ mxe_status mxe_register_matrix(mxe_ctx *ctx, int32_t nrows, int32_t ncols, int64
     if (!row_ptr || (nnz > 0 && (!col_idx || !vals))) return fail(MXE_ERR_INVALID_ARG, "NULL array");
     std::lock_guard<std::recursive_mutex> lk(ctx->mu);
     DeviceGuard g(ctx->device);
+    reap_pending(ctx, false);                           // released memory whose work has ended
     const bool on_dev = flags & MXE_INPUT_DEVICE;
     mxe_status st;
     std::vector<int32_t> hrp, hcol;
@@ -759,6 +756,7 @@ mxe_status mxe_permute(mxe_ctx *ctx, mxe_mat a, uint64_t seed, uint32_t mode, vo
     if (mode & ~(MXE_ROWS | MXE_COLS | MXE_GRADIENT)) return fail(MXE_ERR_INVALID_ARG, "unknown mode bits");
     std::lock_guard<std::recursive_mutex> lk(ctx->mu);
     DeviceGuard g(ctx->device);
+    reap_pending(ctx, false);                           // released memory whose work has ended
     auto A = find_matrix(ctx, a);
     if (!A) return fail(MXE_ERR_NOT_FOUND, "unknown matrix handle");
     hipStream_t s = (hipStream_t)stream;

@@ -161,13 +161,16 @@ struct mxe_ctx {
     int cu_count = 256;
     size_t lds_per_cu = 0, lds_per_block = 0;   // bytes of LDS per CU / per workgroup
     mxe::Server *server = nullptr;      // owned; created and deleted by the serving loop
-    // A released matrix's memory is freed on this stream, after it has waited
-    // for the last use of the matrix on every stream, so releasing never
-    // blocks the host. The use events it waited on are destroyed once they
-    // have fired (or when the context goes).
-    hipStream_t free_stream = nullptr;
-    std::mutex retired_mu;
-    std::vector<hipEvent_t> retired;
+    // Released matrices whose last uses (one event per stream) had not all
+    // finished at release: their memory goes back to the pool at a later
+    // library call that finds those events fired, so releasing never blocks
+    // the host and needs no stream of its own.
+    struct PendingFree {
+        std::vector<hipEvent_t> evs;
+        std::vector<void *> ptrs;
+    };
+    std::mutex pending_mu;
+    std::vector<PendingFree> pending;
 };
 
 namespace mxe {
