@@ -150,13 +150,10 @@ mxe_status mxe_matrix_info(mxe_ctx *ctx, mxe_mat m, mxe_matrix_desc *out);
 /* Releases a handle. A permuted matrix keeps its parent's memory until it is
  * released too, and a batch plan keeps its matrices' memory until the plan is
  * destroyed. Returns MXE_ERR_BUSY while serving work on it is queued or
- * running. When the last reference to a matrix's memory goes, the call
- * returns without waiting and the handle is invalid at once; the memory goes
- * back to the device's pool as soon as the work that library calls queued on
- * that matrix (on each stream they used, up to its last such call) has
- * finished: at once if it has, else at a later register, permute or release
- * call on the context that finds it finished (or when the context is
- * destroyed). The HBM budget counts it as free from the release on. */
+ * running. When the last reference to a matrix's memory goes, the call waits
+ * for the work that library calls queued on that matrix (on each stream they
+ * used, up to its last such call) before the memory is freed; it does not
+ * wait for the rest of the device. */
 mxe_status mxe_release(mxe_ctx *ctx, mxe_mat m);
 
 /* --- measure (Sections 4 and 5) --------------------------------------------- */

@@ -91,44 +91,20 @@ mxe_status reserve(mxe_ctx *ctx, uint64_t bytes) {
     }
 }
 
-// Frees the memory of released matrices whose last uses have all finished
-// (all of them with `all`, once the device is idle).
-static void reap_pending(mxe_ctx *ctx, bool all) {
-    std::lock_guard<std::mutex> lk(ctx->pending_mu);
-    auto &v = ctx->pending;
-    for (size_t i = 0; i < v.size();) {
-        bool done = true;
-        for (hipEvent_t e : v[i].evs)
-            if (!all && hipEventQuery(e) == hipErrorNotReady) done = false;
-        if (!done) {
-            ++i;
-            continue;
-        }
-        for (hipEvent_t e : v[i].evs) (void)hipEventDestroy(e);
-        for (void *p : v[i].ptrs) (void)hipFreeAsync(p, nullptr);
-        v[i] = std::move(v.back());
-        v.pop_back();
-    }
-}
-
-// When the last reference goes, the memory returns to the pool at once if
-// the work each stream queued on the matrix (its last recorded use) has
-// finished, else at a later library call that finds it finished; the host
-// waits for nothing and unrelated work is never waited for.
+// When the last reference goes, the work each stream queued on the matrix
+// (its last recorded use) finishes before the memory returns to the pool;
+// other streams and unrelated work are not waited for.
 std::shared_ptr<Matrix> make_matrix(mxe_ctx *ctx) {
     int dev = ctx->device;
     return std::shared_ptr<Matrix>(new Matrix(), [ctx, dev](Matrix *m) {
         DeviceGuard g(dev);
-        mxe_ctx::PendingFree pf;
-        for (const Matrix::Use &u : m->uses) pf.evs.push_back(u.ev);
-        pf.ptrs = std::move(m->allocs);
-        {
-            std::lock_guard<std::mutex> lk(ctx->pending_mu);
-            ctx->pending.push_back(std::move(pf));
+        for (const Matrix::Use &u : m->uses) {
+            (void)hipEventSynchronize(u.ev);
+            (void)hipEventDestroy(u.ev);
         }
+        for (void *p : m->allocs) (void)hipFreeAsync(p, nullptr);
         ctx->used -= m->bytes;
         delete m;
-        reap_pending(ctx, false);
     });
 }
 
@@ -678,8 +654,6 @@ mxe_status mxe_destroy(mxe_ctx *ctx) {
         (void)hipDeviceSynchronize();
         ctx->plans.clear();
         ctx->mats.clear();
-        (void)hipDeviceSynchronize();
-        reap_pending(ctx, true);
     }
     delete ctx;
     return MXE_OK;
@@ -697,7 +671,6 @@ mxe_status mxe_register_matrix(mxe_ctx *ctx, int32_t nrows, int32_t ncols, int64
     if (!row_ptr || (nnz > 0 && (!col_idx || !vals))) return fail(MXE_ERR_INVALID_ARG, "NULL array");
     std::lock_guard<std::recursive_mutex> lk(ctx->mu);
     DeviceGuard g(ctx->device);
-    reap_pending(ctx, false);                           // released memory whose work has ended
     const bool on_dev = flags & MXE_INPUT_DEVICE;
     mxe_status st;
     std::vector<int32_t> hrp, hcol;
@@ -756,7 +729,6 @@ mxe_status mxe_permute(mxe_ctx *ctx, mxe_mat a, uint64_t seed, uint32_t mode, vo
     if (mode & ~(MXE_ROWS | MXE_COLS | MXE_GRADIENT)) return fail(MXE_ERR_INVALID_ARG, "unknown mode bits");
     std::lock_guard<std::recursive_mutex> lk(ctx->mu);
     DeviceGuard g(ctx->device);
-    reap_pending(ctx, false);                           // released memory whose work has ended
     auto A = find_matrix(ctx, a);
     if (!A) return fail(MXE_ERR_NOT_FOUND, "unknown matrix handle");
     hipStream_t s = (hipStream_t)stream;

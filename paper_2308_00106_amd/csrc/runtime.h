@@ -78,7 +78,7 @@ struct Matrix {
     std::atomic<int> busy{0};           // serving requests queued or running
     std::vector<void *> allocs;         // device allocations to free
     // per stream, an event recorded after the last work queued there on this
-    // matrix: its memory is freed behind these, never behind the whole device
+    // matrix: freeing waits for these, never for the whole device
     struct Use {
         hipStream_t s;
         hipEvent_t ev;
@@ -161,16 +161,6 @@ struct mxe_ctx {
     int cu_count = 256;
     size_t lds_per_cu = 0, lds_per_block = 0;   // bytes of LDS per CU / per workgroup
     mxe::Server *server = nullptr;      // owned; created and deleted by the serving loop
-    // Released matrices whose last uses (one event per stream) had not all
-    // finished at release: their memory goes back to the pool at a later
-    // library call that finds those events fired, so releasing never blocks
-    // the host and needs no stream of its own.
-    struct PendingFree {
-        std::vector<hipEvent_t> evs;
-        std::vector<void *> ptrs;
-    };
-    std::mutex pending_mu;
-    std::vector<PendingFree> pending;
 };
 
 namespace mxe {

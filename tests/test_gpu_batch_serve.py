@@ -386,11 +386,11 @@ def test_carry_variants_on_two_streams(ctx, family):
     ctx.release(A)
 
 
-def test_release_frees_behind_queued_products(ctx):
+def test_release_waits_for_queued_products(ctx):
     """A matrix released while products on it are still queued on a side
-    stream is freed behind them, in stream order: they still read intact
-    memory, and a matrix registered, permuted and multiplied right after on
-    the default stream (its memory may come from the freed blocks) is exact."""
+    stream keeps its memory until they have ended: they read intact memory,
+    and a matrix registered, permuted and multiplied right after on the
+    default stream (its memory may come from the freed blocks) is exact."""
     A0 = synth.clustered_n2m(3, n=400_000)
     A = ctx.register(A0, "f64")
     B = ctx.permute(A, 11)
