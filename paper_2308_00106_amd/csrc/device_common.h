@@ -8,6 +8,16 @@ namespace mxe {
 
 constexpr int kWave = 64;
 
+// A pointer the caller knows to address device memory, in a form the compiler
+// can prove it of. Pointers read from memory (a batch's descriptors) are
+// otherwise generic, and accesses through them compile to flat instructions,
+// which also count against the LDS wait counter: every LDS wait then waits
+// for all loads in flight as well.
+template <typename T>
+__device__ __attribute__((always_inline)) inline T *as_global(T *p) {
+    return (T *)(__attribute__((address_space(1))) T *)(uintptr_t)p;
+}
+
 // ---------------------------------------------------------------------------
 // Random keys. The permutation of n items is the stable ascending order of
 // key(s, i), the i-th output (i = 0, 1, ...) of SplitMix64 started at state s

@@ -39,13 +39,17 @@ batch_unit(const BatchDesc &d, int32_t u, int q, unsigned char *smem, int32_t (*
     asm volatile("v_mov_b32 %0, %1" : "=v"(tid) : "v"((int)threadIdx.x));
     if (d.slab_off) {
         T *yp = reinterpret_cast<T *>(smem);
-        const V *sv = (const V *)d.slab_val;
-        const T *X = (const T *)d.X;
-        T *Y = (T *)d.Y;
+        const V *sv = as_global((const V *)d.slab_val);
+        const T *X = as_global((const T *)d.X);
+        T *Y = as_global((T *)d.Y);
+        const int32_t *so = as_global(d.slab_off);
+        const uint32_t *si = as_global(d.slab_idx);
+        void *const *yc = d.ycol ? as_global(d.ycol) : nullptr;
+        const int64_t *ycl = d.ycol_ld ? as_global(d.ycol_ld) : nullptr;
 #define MXE_BATCH_SLAB(KMV)                                                                        \
-    slab_block<V, T, KMV, 0, false, kBatchInflight>(d.slab, u, q, d.slab_off, d.slab_idx, sv, d.k,  \
-                                                   X, d.ldx, Y, d.ldy, d.vec_x, yp, soff, tid,    \
-                                                   nullptr, 0, 0, d.ycol, d.ycol_ld)
+    slab_block<V, T, KMV, 0, false, kBatchInflight>(d.slab, u, q, so, si, sv, d.k, X, d.ldx, Y,     \
+                                                   d.ldy, d.vec_x, yp, soff, tid, nullptr, 0, 0,  \
+                                                   yc, ycl)
         switch (d.slab.kclass) {
         case 1: MXE_BATCH_SLAB(1); break;
         case 2: MXE_BATCH_SLAB(2); break;
@@ -57,9 +61,11 @@ batch_unit(const BatchDesc &d, int32_t u, int q, unsigned char *smem, int32_t (*
     } else {
         const int32_t r0 = u * d.rows_per_tile;
         const int32_t r1 = min(d.nrows, r0 + d.rows_per_tile);
-        rows_runtime<V, T, kBatchBlock>(d.rp, d.col, (const V *)d.val, d.k, (const T *)d.X, d.ldx,
-                                       (T *)d.Y, d.ldy, d.lanes, d.kclass, r0, r1, tid, d.ycol,
-                                       d.ycol_ld);
+        rows_runtime<V, T, kBatchBlock>(as_global(d.rp), as_global(d.col), as_global((const V *)d.val),
+                                       d.k, as_global((const T *)d.X), d.ldx, as_global((T *)d.Y),
+                                       d.ldy, d.lanes, d.kclass, r0, r1, tid,
+                                       d.ycol ? as_global(d.ycol) : nullptr,
+                                       d.ycol_ld ? as_global(d.ycol_ld) : nullptr);
     }
 }
 

@@ -421,8 +421,8 @@ __global__ __launch_bounds__(kBlock) void k_copy_cols(int32_t n, int32_t k, cons
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_pack_cols(const PackCols *__restrict__ table) {
     const PackCols e = table[blockIdx.y];
-    const T *src = (const T *)e.src;
-    T *dst = (T *)e.dst + e.c0;
+    const T *src = as_global((const T *)e.src);
+    T *dst = as_global((T *)e.dst) + e.c0;
     const int64_t total = (int64_t)e.n * e.k;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
          i += (int64_t)gridDim.x * blockDim.x) {

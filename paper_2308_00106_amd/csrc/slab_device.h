@@ -156,7 +156,7 @@ slab_block(const SlabGeom &g, int32_t block, int xcd, const int32_t *__restrict_
         const int64_t row = row0 + i / KM;
         const int q = i % KM;
         if (row < g.nrows && (KM == 1 || q < k)) {
-            if (ycol) static_cast<T *>(ycol[q])[row * ycol_ld[q]] = yp[i];
+            if (ycol) as_global(static_cast<T *>(ycol[q]))[row * ycol_ld[q]] = yp[i];
             else Y[row * ldy + q] = yp[i];
         }
     }

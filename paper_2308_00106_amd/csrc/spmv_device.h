@@ -59,7 +59,7 @@ __device__ inline void rows_runtime(const int32_t *__restrict__ rp, const int32_
         }
         for (int off = L / 2; off >= KM; off >>= 1) acc += __shfl_xor(acc, off);
         if (el == 0 && active) {
-            if (ycol) static_cast<T *>(ycol[q])[(int64_t)row * ycol_ld[q]] = acc;
+            if (ycol) as_global(static_cast<T *>(ycol[q]))[(int64_t)row * ycol_ld[q]] = acc;
             else Y[(int64_t)row * ldy + q] = acc;
         }
     }
