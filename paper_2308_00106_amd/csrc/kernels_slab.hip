@@ -160,18 +160,32 @@ __global__ __launch_bounds__(kSlabBlock) void k_spmv_slab(SlabGeom g, const int3
                                                           const T *__restrict__ X, int64_t ldx,
                                                           T *__restrict__ Y, int64_t ldy,
                                                           int vec_x, const int32_t *__restrict__ wstart,
-                                                          int32_t win) {
+                                                          int32_t win, int prio) {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     __shared__ int32_t soff[kSubBlocks][kSlabMax + 1];
     T *yp = reinterpret_cast<T *>(smem);
     if constexpr (WIN) {
         T *xw = yp + slab_window_offset(g, (int)sizeof(T)) / sizeof(T);
         slab_block<V, T, KM, SR, true>(g, blockIdx.x, blockIdx.x % 8, off, idx, val, k, X, ldx, Y,
-                                       ldy, vec_x, yp, soff, threadIdx.x, xw, wstart[blockIdx.x], win);
+                                       ldy, vec_x, yp, soff, threadIdx.x, xw, wstart[blockIdx.x], win,
+                                       nullptr, nullptr, prio != 0);
     } else {
         slab_block<V, T, KM, SR>(g, blockIdx.x, blockIdx.x % 8, off, idx, val, k, X, ldx, Y, ldy,
-                                 vec_x, yp, soff, threadIdx.x);
+                                 vec_x, yp, soff, threadIdx.x, nullptr, 0, 0, nullptr, nullptr,
+                                 prio != 0);
     }
+}
+
+// Whether the wavefronts raise their priority around the x gathers (one
+// right-hand side): with an x window in LDS, and with one workgroup per CU
+// (no more blocks than CUs). Measured on the n = 2M FP64 products; with two
+// workgroups per CU and no window it made the product slower.
+static int gather_prio(const SlabGeom &g, int32_t win) {
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return 0;
+    return win > 0 || g.blocks <= cus;
 }
 
 template <typename V, typename T, int KM, int SR>
@@ -185,13 +199,13 @@ hipError_t slab_launch(const SlabGeom &g, const int32_t *off, const uint32_t *id
             lds = slab_window_offset(g, (int)sizeof(T)) + (size_t)win * KM * sizeof(T);
             hipLaunchKernelGGL((k_spmv_slab<V, T, KM, SR, true>), dim3(g.blocks), dim3(kSlabBlock),
                                lds, s, g, off, idx, (const V *)val, k, (const T *)X, ldx, (T *)Y,
-                               ldy, vec_x, wstart, win);
+                               ldy, vec_x, wstart, win, gather_prio(g, win));
             return hipGetLastError();
         }
     }
     hipLaunchKernelGGL((k_spmv_slab<V, T, KM, SR, false>), dim3(g.blocks), dim3(kSlabBlock), lds, s,
                        g, off, idx, (const V *)val, k, (const T *)X, ldx, (T *)Y, ldy, vec_x,
-                       (const int32_t *)nullptr, 0);
+                       (const int32_t *)nullptr, 0, gather_prio(g, 0));
     return hipGetLastError();
 }
 

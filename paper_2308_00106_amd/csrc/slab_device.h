@@ -48,13 +48,16 @@ template <> struct SlabVal<uint16_t, float> {
 // gathering it (the same values, so the same sums).
 // ycol (may be null): column q of the result goes to ycol[q] (its row 0)
 // with leading dimension ycol_ld[q] instead of Y + q with ldy.
+// prio (one right-hand side): the wavefront raises its issue priority while
+// it sends out a batch's x gathers and drops it for the reductions.
 template <typename V, typename T, int KM, int SR, bool WIN = false, int IF = 0>
 __device__ __attribute__((always_inline)) inline void
 slab_block(const SlabGeom &g, int32_t block, int xcd, const int32_t *__restrict__ off,
            const uint32_t *__restrict__ idx, const V *__restrict__ val, int32_t k,
            const T *__restrict__ X, int64_t ldx, T *__restrict__ Y, int64_t ldy, int vec_x,
            T *yp, int32_t (*soff)[kSlabMax + 1], int tid, T *xw = nullptr, int32_t w0 = 0,
-           int32_t win = 0, void *const *ycol = nullptr, const int64_t *ycol_ld = nullptr) {
+           int32_t win = 0, void *const *ycol = nullptr, const int64_t *ycol_ld = nullptr,
+           bool prio = false) {
     using S = Semiring<SR, T>;
     const int wave = tid / kWave, lane = tid % kWave;
     const int32_t R = g.rows_per_block;
@@ -94,6 +97,9 @@ slab_block(const SlabGeom &g, int32_t block, int xcd, const int32_t *__restrict_
         for (int32_t c = b; c < e; c += kD * kWave) {
             if (c != b) load_batch(c, e);                     // the first batch is already loaded
             T xv[kD][KM];
+            if constexpr (KM == 1) {
+                if (prio) __builtin_amdgcn_s_setprio(2);
+            }
 #pragma unroll
             for (int j = 0; j < kD; ++j) {
                 const bool v = u[j] != 0xffffffffu;
@@ -121,6 +127,9 @@ slab_block(const SlabGeom &g, int32_t block, int xcd, const int32_t *__restrict_
                 }
 #pragma unroll
                 for (int q = 0; q < KM; ++q) xv[j][q] = (v && (KM == 1 || q < k)) ? xr[q] : T(0);
+            }
+            if constexpr (KM == 1) {
+                if (prio) __builtin_amdgcn_s_setprio(0);
             }
 #pragma unroll
             for (int j = 0; j < kD; ++j) {
