@@ -165,8 +165,10 @@ slab_block(const SlabGeom &g, int32_t block, int xcd, const int32_t *__restrict_
         const int64_t row = row0 + i / KM;
         const int q = i % KM;
         if (row < g.nrows && (KM == 1 || q < k)) {
-            if (ycol) as_global(static_cast<T *>(ycol[q]))[row * ycol_ld[q]] = yp[i];
-            else Y[row * ldy + q] = yp[i];
+            // y is streamed out: non-temporal stores leave no dirty lines in
+            // the L2 for the end of the launch to write back
+            if (ycol) __builtin_nontemporal_store(yp[i], &as_global(static_cast<T *>(ycol[q]))[row * ycol_ld[q]]);
+            else __builtin_nontemporal_store(yp[i], &Y[row * ldy + q]);
         }
     }
 }
